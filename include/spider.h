@@ -1,0 +1,221 @@
+/*
+ * spider.h -- C ABI of the MI355X (gfx950) strided-swap stencil library.
+ *
+ * The library applies iterated 2-D / 3-D stencils (SPIDER, Sec. 2.2: each
+ * point becomes a weighted linear combination of its radius-r neighbourhood,
+ * repeated over time steps, each step reading only the previous one) by
+ * lowering every kernel row to a banded matrix product Y = K X (Sec. 3.1.1),
+ * permuting the band's columns ahead of time with a strided swap so that every
+ * group of four columns holds at most two non-zeros (Sec. 3.1.2, Fig. 5), and
+ * permuting the input rows on the fly inside the register gather so the product
+ * is unchanged (Sec. 3.2).  The product runs on the gfx950 structured-sparse
+ * matrix instruction (v_smfmac_f32_16x16x64_{f16,bf16}) or, for comparison, on
+ * the dense one (v_mfma_f32_16x16x32_{f16,bf16}); a plain direct-sum engine
+ * serves fp32 / fp64 grids.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Every function returns a spider_status and never throws.  On failure a
+ *    human-readable message is available from spider_last_error() (per thread).
+ *  - Grids are interior-only, contiguous, row-major with x fastest:
+ *    2-D grid[y][x], 3-D grid[z][y][x]; `shape` lists extents slowest first.
+ *    The halo is a fixed zero (Dirichlet-0) boundary of width r on every side.
+ *  - Coefficients are fp64, (2r+1)^ndim of them, laid out w[dz][dy][dx] with
+ *    each index 0..2r; w[o] multiplies x[p + o - r] (correlation, no flip).
+ *  - Device pointers are plain HIP device addresses (e.g. from a PyTorch
+ *    tensor's data_ptr()); `stream` is a hipStream_t passed as void* (NULL =
+ *    the null stream).  The caller owns every buffer it passes in.
+ *  - Work is asynchronous on `stream`: argument and launch errors are returned
+ *    at once; device faults surface at the caller's next synchronisation.
+ */
+#ifndef SPIDER_H
+#define SPIDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPIDER_OK = 0,
+    SPIDER_ERR_INVALID = 1,     /* bad argument (null pointer, size, radius, dtype...) */
+    SPIDER_ERR_UNSUPPORTED = 2, /* valid request this build does not run (e.g. sparse fp32) */
+    SPIDER_ERR_OOM = 3,         /* device or host allocation failed / over budget */
+    SPIDER_ERR_HIP = 4,         /* a HIP runtime call failed */
+    SPIDER_ERR_NOT_READY = 5,   /* ticket still running */
+    SPIDER_ERR_BUSY = 6,        /* server queue full */
+    SPIDER_ERR_CLOSED = 7       /* server shut down / ticket unknown */
+} spider_status;
+
+typedef enum { SPIDER_F64 = 0, SPIDER_F32 = 1, SPIDER_F16 = 2, SPIDER_BF16 = 3 } spider_dtype;
+
+typedef enum {
+    SPIDER_ENGINE_AUTO = 0,   /* sparse for 16-bit carries, direct otherwise */
+    SPIDER_ENGINE_SPARSE = 1, /* strided swap + v_smfmac (16-bit operands only) */
+    SPIDER_ENGINE_DENSE = 2,  /* same band and gather on dense v_mfma (16-bit operands) */
+    SPIDER_ENGINE_DIRECT = 3  /* plain neighbour sum on the vector ALUs (fp32 / fp64 carries) */
+} spider_engine;
+
+/* Plan options.  Zero-initialise and set what you need; spider_opts_default fills defaults. */
+typedef struct {
+    int carry;     /* spider_dtype of the grids passed to apply (default SPIDER_F16) */
+    int engine;    /* spider_engine (default AUTO) */
+    int split;     /* coefficient split for 16-bit operands: 1 = w rounded once,
+                      2 = w_hi + w_lo (default); ignored by the direct engine */
+    int tile_h;    /* output rows per wavefront segment, 0 = chosen by the autotuner */
+    int use_graph; /* 1 = capture each (in, out, steps) time loop once as a hipGraph and
+                      replay it (default), 0 = launch every step */
+    int reserved[3];
+} spider_opts;
+
+typedef struct spider_plan_s* spider_plan_t;
+typedef struct spider_server_s* spider_server_t;
+
+/* Fill `o` with the defaults listed above.  Returns SPIDER_ERR_INVALID if o is NULL. */
+spider_status spider_opts_default(spider_opts* o);
+
+/*
+ * spider_plan: offline transformation (Sec. 3.1, done once per stencil; the paper
+ * reports it as a small rule-based cost outside the timed loop, Sec. 4.2).
+ *   coeffs  host fp64 array, (2r+1)^ndim, layout above; copied, not retained
+ *   ndim    2 or 3
+ *   shape   host array of ndim extents, each in [1, 2^31)
+ *   radius  1..7 (r = 7 is the largest radius the paper works through, Sec. 3.2)
+ *   opts    NULL for defaults
+ *   out     receives the plan handle
+ * Builds, per kernel row with a non-zero tap, the banded matrix, pads it, applies
+ * the strided column swap, splits coefficients into 16-bit hi/lo parts, compresses
+ * to 2:4 values + 2-bit indices and packs them in the gfx950 lane order; uploads
+ * them and allocates one grid-sized scratch buffer on the current HIP device.
+ * Errors: INVALID (arguments), UNSUPPORTED (e.g. sparse engine with an fp32/fp64
+ * carry), OOM, HIP.  The plan is immutable after creation and owns its device memory.
+ */
+spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, int radius,
+                          const spider_opts* opts, spider_plan_t* out);
+
+/*
+ * spider_apply: out = S^steps(in) on `stream` (Jacobi steps, zero halo).
+ *   in, out  device grids of the plan's shape in the plan's carry dtype; `in` is
+ *            never written unless in == out (allowed); steps == 0 copies.
+ *   steps    >= 0
+ * The plan's scratch buffer holds intermediate steps, so two applies of one plan
+ * must not overlap in time (use one plan per concurrent stream).
+ * Errors: INVALID (null plan/pointer, steps < 0), HIP (launch failure).
+ */
+spider_status spider_apply(spider_plan_t plan, const void* in, void* out, int steps, void* stream);
+
+/* Release the plan's device memory and cached graphs.  NULL is accepted. */
+spider_status spider_plan_destroy(spider_plan_t plan);
+
+/*
+ * spider_plan_info: describe a plan (host query, no device work).
+ *   engine, carry, tile_h, nrows_nonzero (kernel rows on the matrix path),
+ *   scratch_bytes (device bytes the plan owns).  Any output pointer may be NULL.
+ */
+spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int* tile_h,
+                               int* nrows_nonzero, size_t* scratch_bytes);
+
+/*
+ * Batched apply (one launch per time step over the tiles of every grid).
+ * Runs grids of uneven size and stencil shape together: at time step s every
+ * grid i with steps[i] > s advances by one step.  The plans must share the
+ * carry dtype and use the sparse or dense engine; grids may be 2-D or 3-D.
+ *   n       number of grids, 1..4096
+ *   plans, ins, outs, steps: host arrays of n entries, as for spider_apply.
+ * Errors: INVALID, UNSUPPORTED (mixed carries or direct-engine plans), HIP.
+ */
+spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* const* ins,
+                                 void* const* outs, const int* steps, void* stream);
+
+/* ------------------------------------------------------------------ serving */
+
+/*
+ * spider_server_create: start a continuous-batching request loop on the
+ * current HIP device.  Requests are admitted while their device footprint
+ * (two grid-sized buffers of the plan's carry dtype) fits in `hbm_budget_bytes`
+ * and a slot is free (max_slots); admitted requests share every round's
+ * batched launch, and a request that arrives while others run joins at the
+ * next round.  Grid state stays on the device between rounds.
+ */
+spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue,
+                                   spider_server_t* out);
+
+/*
+ * spider_submit: enqueue out = S^steps(in) for `plan`.  `in` and `out` are
+ * device buffers owned by the caller that must stay valid until the ticket is
+ * done; `in` is read once at admission.  Returns BUSY if the queue is full,
+ * OOM if the request alone exceeds the budget, INVALID on bad arguments.
+ */
+spider_status spider_submit(spider_server_t srv, spider_plan_t plan, const void* in, void* out,
+                            int steps, uint64_t* ticket);
+
+/* spider_poll: *done = 1 once the result is in `out` (then *result holds its status). */
+spider_status spider_poll(spider_server_t srv, uint64_t ticket, int* done, spider_status* result);
+
+/*
+ * spider_server_stats: latency of completed requests in microseconds (submit ->
+ * result written), percentiles over all completed tickets, and totals.
+ */
+spider_status spider_server_stats(spider_server_t srv, double* p50_us, double* p99_us,
+                                  uint64_t* completed, double* stencil_updates);
+
+/* Stop the loop: finishes admitted requests, fails queued ones with CLOSED, frees memory. */
+spider_status spider_server_destroy(spider_server_t srv);
+
+/* ------------------------------------------------------------------ host-side introspection
+ * These run on the host only (no HIP call); they expose the offline transformation
+ * so it can be checked without a GPU.
+ */
+
+/*
+ * spider_gather_positions: window position of every K slot of one 32-column band
+ * as the gfx950 gather reads it.  pos[k], k = 0..31, is the band column (0..31)
+ * whose input row feeds slot k; a permutation of 0..31.  The band of an output
+ * chunk of 16 points at x0 covers input columns x0-8 .. x0+23.
+ */
+spider_status spider_gather_positions(int pos[32]);
+
+/*
+ * spider_swap_columns: the strided column swap of Sec. 3.1.2 on an L x 2L band
+ * (Fig. 5 stage 2): perm[j] = original column now at column j, j = 0..2L-1.
+ *   granularity 1: element columns, odd j < L exchanged with j + L (the paper's rule)
+ *   granularity 2: the same rule on pairs of columns (32-bit units of 16-bit data)
+ * Errors: INVALID for L < 2, L odd, or granularity not 1/2 (L must be even for 2).
+ */
+spider_status spider_swap_columns(int L, int granularity, int* perm);
+
+/*
+ * spider_compress_24: 2:4 compression of a rows x cols matrix (cols % 4 == 0) whose
+ * every group of 4 has at most 2 non-zeros (Fig. 5 stage 3).  vals is rows x cols/2,
+ * meta is rows x cols/2 2-bit positions (one byte each, 0..3), increasing within a
+ * group; a group with one non-zero keeps a zero placeholder at the next position
+ * (at position 2 if the non-zero is at 3), an all-zero group uses positions 0, 1.
+ * Errors: INVALID if a group holds more than 2 non-zeros or sizes are bad.
+ */
+spider_status spider_compress_24(const double* m, int rows, int cols, double* vals, uint8_t* meta);
+
+/*
+ * spider_pack_row: the packed smfmac operands of one kernel row as the 2-D/3-D
+ * kernels load them.  row: 2r+1 fp64 taps along x; operand SPIDER_F16/BF16; split 1/2.
+ *   a_bits  64 lanes x 8 16-bit values (compressed A of the 16 x 64 operand
+ *           [K'_hi | K'_lo], lane-major)
+ *   idx     64 lanes x 16-bit index field (2 bits per compressed value)
+ *   dense_bits  64 lanes x 16 16-bit values: dense A of K'_hi (8) then K'_lo (8), or NULL
+ * Errors: INVALID.
+ */
+spider_status spider_pack_row(const double* row, int radius, int operand, int split, uint16_t* a_bits,
+                              uint16_t* idx, uint16_t* dense_bits);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* spider_last_error(void);
+
+/* Library version string. */
+const char* spider_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIDER_H */
