@@ -1,0 +1,46 @@
+// Internal state behind the C ABI handles.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/spider.h"
+#include "kernels.h"
+
+struct spider_plan_s {
+  int ndim = 2;
+  int nz = 1, ny = 0, nx = 0;
+  int r = 1;
+  int carry = SPIDER_F16;    // dtype of the grids
+  int operand = SPIDER_F16;  // dtype of the matrix operands (matrix engines)
+  int engine = SPIDER_ENGINE_SPARSE;
+  int split = 2;
+  int tile_h = 0;
+  int use_graph = 1;
+  int device = 0;
+  std::vector<double> coeffs;
+  int nrows = 0;          // kernel rows (lines of taps along x)
+  uint32_t rowmask = 0;   // rows with a non-zero tap
+  void* d_apack = nullptr;
+  void* d_ipack = nullptr;
+  void* d_dpack = nullptr;
+  void* d_coeffs = nullptr;
+  void* d_scratch = nullptr;
+  size_t grid_bytes = 0;
+  spider_impl::BandGrid grid_template{};
+  hipStream_t cap_stream = nullptr;
+  std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
+  std::mutex mu;
+};
+
+namespace spider_impl {
+spider_status fail(spider_status st, const char* fmt, ...);
+spider_status hip_fail(hipError_t e, const char* what);
+void clear_err();
+size_t dtype_bytes(int dt);
+spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
+spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
+}  // namespace spider_impl

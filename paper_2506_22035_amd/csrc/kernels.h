@@ -1,0 +1,52 @@
+// Internal launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace spider_impl {
+
+// Device-side description of one grid for the band (matrix) engines.
+//   Rows are 1-D lines along x; a 2-D grid has nz = 1.
+//   Kernel rows with a non-zero tap are listed in (dz, dy) order; row i's packed
+//   operands are apack[i*64 + lane] (smfmac A), ipack[(i/2)*64 + lane] (index,
+//   16 bits, half i%2) and dpack[(i*64 + lane)*2 + {0,1}] (dense hi, lo).
+struct BandGrid {
+  const void* in;
+  void* out;
+  int nz, ny, nx;
+  int seg_h;          // output rows (2-D) / planes (3-D) per wave segment
+  int nstrips;        // ceil(nx / 256)
+  int nsegs_y;        // 2-D: ceil(ny / seg_h); 3-D: ceil(ny / kRowsY3)
+  int nsegs_z;        // 3-D: ceil(nz / seg_h); 2-D: 1
+  const uint4* apack;
+  const uint32_t* ipack;
+  const uint4* dpack;
+  uint32_t rowmask;   // 2-D: bit a set if kernel row a (dy = a - r) is non-zero;
+                      // 3-D: bit dz*(2r+1)+dy
+  int nblocks;        // waves (workgroups) this grid needs
+};
+
+// Launch one time step of the band engine over `n` grids (batched); all grids
+// share radius r (<= 7), operand dtype (2 = f16, 3 = bf16) and engine
+// (1 = sparse, 2 = dense), and dimensionality.  Grids are described in a
+// device array `grids_dev` (n entries) plus the host copy for sizing.
+hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* grids_dev, const BandGrid* grids_host,
+                         int n, hipStream_t s);
+hipError_t launch_band3d(int r, int operand, int engine, const BandGrid* grids_dev, const BandGrid* grids_host,
+                         int n, hipStream_t s);
+
+// Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
+int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
+
+// Output rows per 3-D wave along y (accumulator block height).
+constexpr int kRowsY3 = 4;
+
+// Plain direct-sum engine (fp32 / fp64 carry).  coeffs_dev holds (2r+1)^ndim
+// taps in the carry dtype.  dtype: 0 = f64, 1 = f32.
+hipError_t launch_direct(int ndim, int r, int dtype, const void* in, void* out, int nz, int ny, int nx,
+                         const void* coeffs_dev, int seg_h, hipStream_t s);
+
+// Rows of the 2-D band wave: stride between wave strips along x.
+constexpr int kStripW = 256;
+
+}  // namespace spider_impl

@@ -1,0 +1,194 @@
+// Band (matrix) engines for 2-D and 3-D grids on gfx950.
+//
+// SPIDER (Sec. 3.1.1) decomposes the stencil kernel into rows; each kernel row
+// applied to a chunk of consecutive output points along x is the banded product
+// Y = K X.  Here the chunk is 16 points (the instruction's M), the band is read
+// through a 32-column window (Fig. 5 padding), and the input window's columns
+// are permuted on the fly by the gather (Sec. 3.2) to match the strided swap
+// applied to K offline, so every group of four K columns has at most two
+// non-zeros and the product runs on v_smfmac (Fig. 1's 2:4 format).
+//
+// Work decomposition (one 64-lane wavefront per workgroup, no cross-wave
+// synchronisation):
+//   2-D: a wave owns a 256-wide strip of x and `seg_h` consecutive output rows.
+//        It streams the seg_h + 2r input rows once.  Input row y feeds output
+//        rows y - r .. y + r through kernel rows 2r .. 0, so 2r+1 accumulators
+//        (16x16 fp32 tiles, rotating) are live and every input row is loaded,
+//        staged and gathered exactly once per strip.
+//   3-D: a wave owns a strip, kRowsY3 output rows in y and `seg_h` planes in z;
+//        it streams planes, and each input line (z, y) feeds the output lines
+//        (z - dz + r, y - dy + r) for every non-zero kernel row (dz, dy).
+#include <hip/hip_runtime.h>
+
+#include "band_common.h"
+#include "kernels.h"
+
+namespace spider_impl {
+
+// ----------------------------------------------------------------------------- 2-D
+
+template <int R, int OP, int ENG, bool ALIGNED>
+__device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int U = (RR >= 5) ? RR : 2 * RR;  // unroll = prefetch depth, multiple of RR
+  const int lane = threadIdx.x;
+  const int strip = w % g.nstrips, seg = w / g.nstrips;
+  const int x0 = strip * kStripW;
+  const int y0 = seg * g.seg_h;
+  const int hrows = min(g.seg_h, g.ny - y0);        // output rows of this segment
+  const int nin = ((hrows + 2 * R + U - 1) / U) * U;  // input rows streamed, padded to U
+  const int nx = g.nx, ny = g.ny;
+
+  // Register-resident kernel operands (Sec. 3.3.1: the kernel matrix bypasses shared memory).
+  u32x4 A[RR], Dh[RR], Dl[RR];
+  uint32_t I[(RR + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < RR; ++a) {
+    if constexpr (ENG == 1) {
+      A[a] = reinterpret_cast<const u32x4*>(g.apack)[a * 64 + lane];
+      Dh[a] = Dl[a] = (u32x4){0, 0, 0, 0};
+    } else {
+      A[a] = (u32x4){0, 0, 0, 0};
+      Dh[a] = reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 0];
+      Dl[a] = reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 1];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < (RR + 1) / 2; ++a) I[a] = (ENG == 1) ? g.ipack[a * 64 + lane] : 0u;
+
+  // Operand loads must land before the streaming loop so the loop's wait counts
+  // only track the staged rows.
+  __builtin_amdgcn_s_waitcnt(0);
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const uint32_t lvoff = chunk_voffset(x0, lane);
+  const uint32_t ovoff = out_voffset(x0, lane);
+  const int lw = chunk_lds_offset(lane, U * kLdsRowDw);  // lanes >= 34: spare area
+  const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
+
+  // Input rows are streamed in bodies of U rows: a body first moves its U staged
+  // rows (loaded during the previous body) into U LDS rows, then issues the loads
+  // of the next body, then gathers and multiplies row by row.  Input row j is
+  // y = y0 - R + j; stg[q] holds row j with j % U == q.
+  u32x4 stg[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int y = y0 - R + q;
+    const bool valid = q < hrows + 2 * R && y >= 0 && y < ny;
+    stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
+  }
+  f32x4 acc[RR];
+#pragma unroll
+  for (int s = 0; s < RR; ++s) acc[s] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  for (int jb = 0; jb < nin; jb += U) {
+    wave_lds_sync();  // previous body's gathers are issued before its LDS rows are reused
+#pragma unroll
+    for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int jn = jb + U + q;
+      const int y = y0 - R + jn;
+      const bool valid = jn < hrows + 2 * R && y >= 0 && y < ny;
+      stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = jb + q;
+      const uint32_t* lrow = lds + q * kLdsRowDw;
+      const u32x4 b = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+      // Input row j feeds output row i = j - a through kernel row a; its accumulator
+      // slot is (j - a) mod RR = (q - a) mod RR because U is a multiple of RR.
+#pragma unroll
+      for (int a = 0; a < RR; ++a) {
+        const int slot = ((q - a) % RR + RR) % RR;
+        if (a & 1)
+          acc[slot] = band_mma<OP, ENG, 1>(acc[slot], A[a], Dh[a], Dl[a], I[a / 2], b);
+        else
+          acc[slot] = band_mma<OP, ENG, 0>(acc[slot], A[a], Dh[a], Dl[a], I[a / 2], b);
+      }
+      // Output row j - 2r has received its last kernel row: store it, recycle the slot.
+      const int i = j - 2 * R;
+      const int fs = (q + 1) % RR;
+      const bool ovalid = i >= 0 && i < hrows;
+      store_out<OP, ALIGNED>(line_rsrc(g.out, (size_t)(y0 + i) * nx, nx, ovalid, 2), ovoff, acc[fs]);
+      acc[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+  }
+}
+
+template <int R, int OP, int ENG, bool ALIGNED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 3 ? 4 : 2))) void band2d_kernel(BandGrid g) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int U = (RR >= 5) ? RR : 2 * RR;
+  __shared__ uint32_t lds[U * kLdsRowDw + kLdsSpareDw];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band2d_body<R, OP, ENG, ALIGNED>(g, w, lds);
+}
+
+// ----------------------------------------------------------------------------- dispatch
+
+template <int OP, int ENG, bool AL>
+static hipError_t dispatch2d(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  switch (r) {
+    case 1: hipLaunchKernelGGL((band2d_kernel<1, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band2d_kernel<2, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band2d_kernel<3, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 4: hipLaunchKernelGGL((band2d_kernel<4, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 5: hipLaunchKernelGGL((band2d_kernel<5, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 6: hipLaunchKernelGGL((band2d_kernel<6, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 7: hipLaunchKernelGGL((band2d_kernel<7, OP, ENG, AL>), grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* /*grids_dev*/, const BandGrid* grids_host,
+                         int n, hipStream_t s) {
+  if (n != 1) return hipErrorInvalidValue;
+  const BandGrid& g = grids_host[0];
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2 && engine == 1) return al ? dispatch2d<2, 1, true>(r, g, s) : dispatch2d<2, 1, false>(r, g, s);
+  if (operand == 2 && engine == 2) return al ? dispatch2d<2, 2, true>(r, g, s) : dispatch2d<2, 2, false>(r, g, s);
+  if (operand == 3 && engine == 1) return al ? dispatch2d<3, 1, true>(r, g, s) : dispatch2d<3, 1, false>(r, g, s);
+  if (operand == 3 && engine == 2) return al ? dispatch2d<3, 2, true>(r, g, s) : dispatch2d<3, 2, false>(r, g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_band3d(int, int, int, const BandGrid*, const BandGrid*, int, hipStream_t) {
+  return hipErrorNotSupported;
+}
+
+}  // namespace spider_impl
+
+namespace spider_impl {
+
+// Resident workgroups per CU of the 2-D band kernel (for sizing the segment height).
+template <int OP, int ENG, bool AL>
+static int occ2d(int r) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (r) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<1, OP, ENG, AL>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<2, OP, ENG, AL>, 64, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<3, OP, ENG, AL>, 64, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<4, OP, ENG, AL>, 64, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<5, OP, ENG, AL>, 64, 0); break;
+    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<6, OP, ENG, AL>, 64, 0); break;
+    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_kernel<7, OP, ENG, AL>, 64, 0); break;
+    default: break;
+  }
+  return e == hipSuccess ? nb : 0;
+}
+
+int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned) {
+  if (operand == 2 && engine == 1) return aligned ? occ2d<2, 1, true>(r) : occ2d<2, 1, false>(r);
+  if (operand == 2 && engine == 2) return aligned ? occ2d<2, 2, true>(r) : occ2d<2, 2, false>(r);
+  if (operand == 3 && engine == 1) return aligned ? occ2d<3, 1, true>(r) : occ2d<3, 1, false>(r);
+  if (operand == 3 && engine == 2) return aligned ? occ2d<3, 2, true>(r) : occ2d<3, 2, false>(r);
+  return 0;
+}
+
+}  // namespace spider_impl

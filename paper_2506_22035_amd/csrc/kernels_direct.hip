@@ -1,0 +1,339 @@
+// Direct neighbour-sum engine for fp32 / fp64 grids (the plain GPU path).
+//
+// This is the stencil of SPIDER Sec. 2.2 computed point by point on the vector
+// ALUs, with the same data movement as the band engine: one 64-lane wavefront
+// owns a 256-wide strip of x (each lane 4 consecutive points) and streams input
+// lines through LDS once, keeping the partial sums of the 2r+1 (2-D) or
+// (2r+1) x kRowsY3 (3-D) output lines in flight in registers.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace spider_impl {
+
+namespace {
+
+constexpr int kRsrc3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t drsrc(const void* base, size_t off_elems, int nx, bool valid,
+                                                       int eb) {
+  const char* p = static_cast<const char*>(base) + (valid ? off_elems * eb : 0);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, valid ? nx * eb : 0, kRsrc3);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Geometry of a staged line: x in [x0 - LEAD, x0 + SW + LEAD) with LEAD = 4 ceil(r/4)
+// and strip width SW = 256 - 2 LEAD, so a line is exactly 256 values (one 16-byte
+// load per lane for fp32, two for fp64).  Lanes with 4 lane >= SW compute nothing.
+template <typename T, int R>
+struct Line {
+  static constexpr int LEAD = 4 * ((R + 3) / 4);
+  static constexpr int SW = 256 - 2 * LEAD;
+  static constexpr int ELEMS = 256;
+  static constexpr int EPC = 16 / sizeof(T);                // elements per 16-byte chunk
+  static constexpr int CHUNKS = ELEMS / EPC;
+  static constexpr int LOADS = CHUNKS / 64;                 // 16-byte loads per lane per line
+  static constexpr int WIN = 4 + 2 * LEAD;                  // elements a lane reads per line
+  static constexpr int WCH = WIN / EPC;                     // 16-byte LDS reads per lane per line
+  static constexpr int DW = ELEMS * sizeof(T) / 4;          // dwords per LDS line
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void load_line(u32x4* st, __amdgpu_buffer_rsrc_t rs, int x0, int lane) {
+  using L = Line<T, R>;
+#pragma unroll
+  for (int k = 0; k < L::LOADS; ++k) {
+    const int c = lane + 64 * k;
+    const uint32_t off = (uint32_t)((x0 - L::LEAD) * (int)sizeof(T) + 16 * c);
+    st[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void line_to_lds(uint32_t* lrow, const u32x4* st, int lane) {
+  using L = Line<T, R>;
+#pragma unroll
+  for (int k = 0; k < L::LOADS; ++k) {
+    const int c = lane + 64 * k;
+    *reinterpret_cast<u32x4*>(lrow + 4 * c) = st[k];
+  }
+}
+
+// The WIN values x0 + 4 lane - LEAD + t, t = 0..WIN-1, of one LDS line.
+template <typename T, int R>
+__device__ __forceinline__ void read_window(T* v, const uint32_t* lrow, int lane) {
+  using L = Line<T, R>;
+  const int l = 4 * lane < L::SW ? lane : 0;  // idle lanes read a valid window
+  const u32x4* p = reinterpret_cast<const u32x4*>(lrow) + l * (4 / L::EPC);
+#pragma unroll
+  for (int k = 0; k < L::WCH; ++k) {
+    const u32x4 c = p[k];
+    const T* e = reinterpret_cast<const T*>(&c);
+#pragma unroll
+    for (int t = 0; t < L::EPC; ++t) v[k * L::EPC + t] = e[t];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store4(__amdgpu_buffer_rsrc_t rs, int x0, int lane, const T (&o)[4]) {
+  const uint32_t off = (uint32_t)((x0 + 4 * lane) * (int)sizeof(T));
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b128(
+        (u32x4){__builtin_bit_cast(uint32_t, o[0]), __builtin_bit_cast(uint32_t, o[1]),
+                __builtin_bit_cast(uint32_t, o[2]), __builtin_bit_cast(uint32_t, o[3])},
+        rs, off, 0, 0);
+  } else {
+    const uint64_t a = __builtin_bit_cast(uint64_t, o[0]), b = __builtin_bit_cast(uint64_t, o[1]);
+    const uint64_t c = __builtin_bit_cast(uint64_t, o[2]), d = __builtin_bit_cast(uint64_t, o[3]);
+    __builtin_amdgcn_raw_buffer_store_b128(
+        (u32x4){(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)}, rs, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(
+        (u32x4){(uint32_t)c, (uint32_t)(c >> 32), (uint32_t)d, (uint32_t)(d >> 32)}, rs, off + 16, 0, 0);
+  }
+}
+
+// Last-x guard for grids whose width is not a multiple of 4: a 16-byte store
+// straddling nx would be dropped whole by the range check, so such lanes store
+// element by element.
+template <typename T>
+__device__ __forceinline__ void store_out4(__amdgpu_buffer_rsrc_t rs, int x0, int sw, int nx, int lane,
+                                           const T (&o)[4]) {
+  const int x = x0 + 4 * lane;
+  if (4 * lane >= sw) return;
+  if (x + 4 <= nx) {
+    store4<T>(rs, x0, lane, o);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t off = (uint32_t)((x + k) * (int)sizeof(T));
+      if (x + k < nx) {
+        if constexpr (sizeof(T) == 4)
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, o[k]), rs, off, 0, 0);
+        else
+          __builtin_amdgcn_raw_buffer_store_b64(
+              (uint32_t __attribute__((ext_vector_type(2)))){(uint32_t)__builtin_bit_cast(uint64_t, o[k]),
+                                                             (uint32_t)(__builtin_bit_cast(uint64_t, o[k]) >> 32)},
+              rs, off, 0, 0);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ 2-D
+// acc[m] holds output line j - 2R + m while input line j is applied; input line j
+// feeds it through kernel row a = 2R - m.  After line j, acc[0] is complete and the
+// window shifts by one line.  Lines are staged two ahead.
+
+template <typename T, int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void direct2d_kernel(
+    const T* __restrict__ in, T* __restrict__ out, int ny, int nx, const T* __restrict__ w, int seg_h, int nstrips) {
+  using L = Line<T, R>;
+  constexpr int RR = 2 * R + 1;
+  __shared__ uint32_t lds[2 * L::DW];
+  const int lane = threadIdx.x;
+  const int wv = blockIdx.x;
+  const int strip = wv % nstrips, seg = wv / nstrips;
+  const int x0 = strip * L::SW, y0 = seg * seg_h;
+  const int hrows = min(seg_h, ny - y0);
+  const int nin = hrows + 2 * R;
+  u32x4 st[2][L::LOADS];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int y = y0 - R + q;
+    const bool valid = q < nin && y >= 0 && y < ny;
+    load_line<T, R>(st[q], drsrc(in, (size_t)(valid ? y : 0) * nx, nx, valid, sizeof(T)), x0, lane);
+  }
+  T acc[RR][4];
+#pragma unroll
+  for (int m = 0; m < RR; ++m)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[m][k] = T(0);
+
+  for (int jb = 0; jb < nin; jb += 2) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = jb + q;
+      if (j >= nin) break;
+      wave_sync();
+      line_to_lds<T, R>(lds + q * L::DW, st[q], lane);
+      {
+        const int jn = j + 2, y = y0 - R + jn;
+        const bool valid = jn < nin && y >= 0 && y < ny;
+        load_line<T, R>(st[q], drsrc(in, (size_t)(valid ? y : 0) * nx, nx, valid, sizeof(T)), x0, lane);
+      }
+      wave_sync();
+      T v[L::WIN];
+      read_window<T, R>(v, lds + q * L::DW, lane);
+#pragma unroll
+      for (int m = 0; m < RR; ++m) {
+        const int a = 2 * R - m;
+#pragma unroll
+        for (int t = 0; t < RR; ++t) {
+          const T c = w[a * RR + t];
+          if (c != T(0)) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[m][k] = __builtin_fma(c, v[k + t - R + L::LEAD], acc[m][k]);
+          }
+        }
+      }
+      const int i = j - 2 * R;
+      const bool ovalid = i >= 0;
+      store_out4<T>(drsrc(out, (size_t)(ovalid ? y0 + i : 0) * nx, nx, ovalid, sizeof(T)), x0, L::SW, nx, lane,
+                    acc[0]);
+#pragma unroll
+      for (int m = 0; m < RR - 1; ++m)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[m][k] = acc[m + 1][k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[RR - 1][k] = T(0);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ 3-D
+// A wave owns a strip, kRowsY3 output lines in y and seg_h planes in z, and
+// streams input planes (kRowsY3 + 2R lines each), staged one plane ahead.
+// acc[m][b] holds output line (plane p - 2R + m, y = yb0 + b) while plane p is applied.
+
+template <typename T, int R>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void direct3d_kernel(
+    const T* __restrict__ in, T* __restrict__ out, int nz, int ny, int nx, const T* __restrict__ w, int seg_h,
+    int nstrips, int nsegy) {
+  using L = Line<T, R>;
+  constexpr int RR = 2 * R + 1;
+  constexpr int YB = kRowsY3;
+  constexpr int NL = YB + 2 * R;  // lines per plane
+  __shared__ uint32_t lds[NL * L::DW];
+  const int lane = threadIdx.x;
+  int wv = blockIdx.x;
+  const int strip = wv % nstrips;
+  wv /= nstrips;
+  const int sy = wv % nsegy, sz = wv / nsegy;
+  const int x0 = strip * L::SW, yb0 = sy * YB, z0 = sz * seg_h;
+  const int hz = min(seg_h, nz - z0);
+  const int npl = hz + 2 * R;
+  T acc[RR][YB][4];
+#pragma unroll
+  for (int m = 0; m < RR; ++m)
+#pragma unroll
+    for (int b = 0; b < YB; ++b)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[m][b][k] = T(0);
+  u32x4 st[NL][L::LOADS];
+  auto stage = [&](int pj) {
+    const int z = z0 - R + pj;
+    const bool zvalid = pj < npl && z >= 0 && z < nz;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int y = yb0 - R + l;
+      const bool valid = zvalid && y >= 0 && y < ny;
+      load_line<T, R>(st[l], drsrc(in, ((size_t)(valid ? z : 0) * ny + (valid ? y : 0)) * nx, nx, valid, sizeof(T)),
+                      x0, lane);
+    }
+  };
+  stage(0);
+  for (int pj = 0; pj < npl; ++pj) {
+    wave_sync();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) line_to_lds<T, R>(lds + l * L::DW, st[l], lane);
+    stage(pj + 1);
+    wave_sync();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      T v[L::WIN];
+      read_window<T, R>(v, lds + l * L::DW, lane);
+#pragma unroll
+      for (int m = 0; m < RR; ++m) {
+        const int dz = 2 * R - m;
+#pragma unroll
+        for (int b = 0; b < YB; ++b) {
+          const int dy = l - b;  // input line yb0 - R + l feeds output line yb0 + b
+          if (dy < 0 || dy >= RR) continue;
+#pragma unroll
+          for (int t = 0; t < RR; ++t) {
+            const T c = w[(dz * RR + dy) * RR + t];
+            if (c != T(0)) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) acc[m][b][k] = __builtin_fma(c, v[k + t - R + L::LEAD], acc[m][b][k]);
+            }
+          }
+        }
+      }
+    }
+    const int i = pj - 2 * R;  // output plane complete
+    const bool pvalid = i >= 0;
+#pragma unroll
+    for (int b = 0; b < YB; ++b) {
+      const int y = yb0 + b;
+      const bool valid = pvalid && y < ny;
+      store_out4<T>(drsrc(out, ((size_t)(valid ? z0 + i : 0) * ny + (valid ? y : 0)) * nx, nx, valid, sizeof(T)),
+                    x0, L::SW, nx, lane, acc[0][b]);
+    }
+#pragma unroll
+    for (int m = 0; m < RR - 1; ++m)
+#pragma unroll
+      for (int b = 0; b < YB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[m][b][k] = acc[m + 1][b][k];
+#pragma unroll
+    for (int b = 0; b < YB; ++b)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[RR - 1][b][k] = T(0);
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <typename T>
+static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, int nz, int ny, int nx,
+                                  const void* w, int seg_h, hipStream_t s) {
+  const int sw = 256 - 2 * 4 * ((r + 3) / 4);
+  const int nstrips = (nx + sw - 1) / sw;
+  const T* pin = static_cast<const T*>(in);
+  T* pout = static_cast<T*>(out);
+  const T* pw = static_cast<const T*>(w);
+  if (ndim == 2) {
+    const int nseg = (ny + seg_h - 1) / seg_h;
+    const dim3 grid(nstrips * nseg), block(64);
+    switch (r) {
+#define SPIDER_D2(RV) \
+  case RV: hipLaunchKernelGGL((direct2d_kernel<T, RV>), grid, block, 0, s, pin, pout, ny, nx, pw, seg_h, nstrips); break;
+      SPIDER_D2(1) SPIDER_D2(2) SPIDER_D2(3) SPIDER_D2(4) SPIDER_D2(5) SPIDER_D2(6) SPIDER_D2(7)
+#undef SPIDER_D2
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    const int nsegy = (ny + kRowsY3 - 1) / kRowsY3;
+    const int nsegz = (nz + seg_h - 1) / seg_h;
+    const dim3 grid(nstrips * nsegy * nsegz), block(64);
+    switch (r) {
+#define SPIDER_D3(RV)                                                                                                \
+  case RV:                                                                                                           \
+    hipLaunchKernelGGL((direct3d_kernel<T, RV>), grid, block, 0, s, pin, pout, nz, ny, nx, pw, seg_h, nstrips, nsegy); \
+    break;
+      SPIDER_D3(1) SPIDER_D3(2)
+#undef SPIDER_D3
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_direct(int ndim, int r, int dtype, const void* in, void* out, int nz, int ny, int nx,
+                         const void* coeffs_dev, int seg_h, hipStream_t s) {
+  if (dtype == 0) return direct_dispatch<double>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
+  if (dtype == 1) return direct_dispatch<float>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace spider_impl

@@ -1,0 +1,400 @@
+// C ABI of the stencil library: plan construction (the offline transformation
+// of SPIDER Sec. 3.1), the time loop (Sec. 1: each step reads the previous one),
+// hipGraph capture of that loop, and host-side introspection of the planner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/spider.h"
+#include "api_internal.h"
+#include "kernels.h"
+#include "planner.h"
+
+using namespace spider_impl;
+
+namespace spider_impl {
+
+static thread_local std::string g_err;
+
+spider_status fail(spider_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+spider_status hip_fail(hipError_t e, const char* what) {
+  return fail(SPIDER_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_err() { g_err.clear(); }
+
+size_t dtype_bytes(int dt) {
+  switch (dt) {
+    case SPIDER_F64: return 8;
+    case SPIDER_F32: return 4;
+    case SPIDER_F16:
+    case SPIDER_BF16: return 2;
+    default: return 0;
+  }
+}
+
+// Segment height of the 2-D band kernel: enough rows per wave that one launch
+// fills every CU once (all waves resident, no tail round), but not fewer than
+// 16 rows so the 2r halo rows stay a small fraction of the streamed rows.
+static int auto_tile_h_2d(const spider_plan_s* p) {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  int per_cu = band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
+  if (per_cu <= 0) per_cu = 8;
+  const long long slots = (long long)ncu * per_cu;
+  const long long nstrips = (p->nx + kStripW - 1) / kStripW;
+  long long h = (p->ny * nstrips + slots - 1) / slots;
+  h = std::max<long long>(h, 16);
+  h = std::min<long long>(h, p->ny);
+  return (int)h;
+}
+
+static int auto_tile_h_direct(const spider_plan_s* p) {
+  if (p->ndim == 3) return std::min(p->nz, 32);
+  return std::min(p->ny, 64);
+}
+
+// One time step of the plan from `src` to `dst` on `s`.
+spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
+  hipError_t e;
+  if (p->engine == SPIDER_ENGINE_DIRECT) {
+    e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, src, dst, p->nz, p->ny, p->nx, p->d_coeffs,
+                      p->tile_h, s);
+  } else if (p->ndim == 2) {
+    BandGrid g = p->grid_template;
+    g.in = src;
+    g.out = dst;
+    e = launch_band2d(p->r, p->operand, p->engine, nullptr, &g, 1, s);
+  } else {
+    BandGrid g = p->grid_template;
+    g.in = src;
+    g.out = dst;
+    e = launch_band3d(p->r, p->operand, p->engine, nullptr, &g, 1, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SPIDER_OK;
+}
+
+// Enqueue the whole time loop: buffers b_0 = in, b_1 .. b_steps with b_steps = out,
+// alternating between out and the plan's scratch so that the last step lands in
+// out and `in` is never written (unless in == out).
+spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s) {
+  const size_t bytes = p->grid_bytes;
+  if (steps == 0) {
+    if (in != out) {
+      hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return SPIDER_OK;
+  }
+  const void* src = in;
+  // b_k = out if (steps - k) is even, else scratch.  With in == out and b_1 == out
+  // (steps odd), step 1 would read and write one buffer: copy in to scratch first.
+  if (in == out && (steps - 1) % 2 == 0) {
+    hipError_t e = hipMemcpyAsync(p->d_scratch, in, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    src = p->d_scratch;
+    // now b_1 = out differs from src = scratch, and later steps alternate as usual
+  }
+  for (int k = 1; k <= steps; ++k) {
+    void* dst = ((steps - k) % 2 == 0) ? out : p->d_scratch;
+    if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: step %d reads and writes one buffer", k);
+    spider_status st = launch_step(p, src, dst, s);
+    if (st != SPIDER_OK) return st;
+    src = dst;
+  }
+  return SPIDER_OK;
+}
+
+}  // namespace spider_impl
+
+// =========================================================================== C ABI
+
+extern "C" {
+
+const char* spider_last_error(void) { return g_err.c_str(); }
+
+const char* spider_version(void) { return "spider-mi355x 0.1 (gfx950)"; }
+
+spider_status spider_opts_default(spider_opts* o) {
+  if (!o) return fail(SPIDER_ERR_INVALID, "opts is NULL");
+  std::memset(o, 0, sizeof(*o));
+  o->carry = SPIDER_F16;
+  o->engine = SPIDER_ENGINE_AUTO;
+  o->split = 2;
+  o->tile_h = 0;
+  o->use_graph = 1;
+  return SPIDER_OK;
+}
+
+spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, int radius, const spider_opts* opts,
+                          spider_plan_t* out) {
+  clear_err();
+  if (!out) return fail(SPIDER_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!coeffs || !shape) return fail(SPIDER_ERR_INVALID, "coeffs or shape is NULL");
+  if (ndim != 2 && ndim != 3) return fail(SPIDER_ERR_INVALID, "ndim must be 2 or 3 (got %d)", ndim);
+  if (radius < 1 || radius > 7) return fail(SPIDER_ERR_INVALID, "radius must be in 1..7 (got %d)", radius);
+  for (int i = 0; i < ndim; ++i)
+    if (shape[i] < 1 || shape[i] >= (1LL << 31)) return fail(SPIDER_ERR_INVALID, "shape[%d] out of range", i);
+  spider_opts o;
+  spider_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.carry < SPIDER_F64 || o.carry > SPIDER_BF16) return fail(SPIDER_ERR_INVALID, "bad carry dtype %d", o.carry);
+  int engine = o.engine;
+  const bool low = (o.carry == SPIDER_F16 || o.carry == SPIDER_BF16);
+  if (engine == SPIDER_ENGINE_AUTO) engine = low ? SPIDER_ENGINE_SPARSE : SPIDER_ENGINE_DIRECT;
+  if (engine < SPIDER_ENGINE_SPARSE || engine > SPIDER_ENGINE_DIRECT) return fail(SPIDER_ERR_INVALID, "bad engine");
+  if ((engine == SPIDER_ENGINE_SPARSE || engine == SPIDER_ENGINE_DENSE) && !low)
+    return fail(SPIDER_ERR_UNSUPPORTED,
+                "the matrix engines take 16-bit operands (gfx950 has no fp32/fp64 structured-sparse instruction); "
+                "use the direct engine for fp32/fp64 grids");
+  if (engine == SPIDER_ENGINE_DIRECT && low)
+    return fail(SPIDER_ERR_UNSUPPORTED, "the direct engine runs fp32/fp64 grids only");
+  if (engine != SPIDER_ENGINE_DIRECT && o.split != 1 && o.split != 2)
+    return fail(SPIDER_ERR_INVALID, "split must be 1 or 2");
+  if (engine == SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 2)
+    return fail(SPIDER_ERR_UNSUPPORTED, "direct engine: 3-D radius up to 2");
+  if (engine != SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 1)
+    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines: 3-D radius 1 only in this build");
+  if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
+
+  auto* p = new spider_plan_s();
+  p->ndim = ndim;
+  p->r = radius;
+  p->nz = ndim == 3 ? (int)shape[0] : 1;
+  p->ny = (int)shape[ndim - 2];
+  p->nx = (int)shape[ndim - 1];
+  p->carry = o.carry;
+  p->operand = low ? o.carry : SPIDER_F16;
+  p->engine = engine;
+  p->split = o.split;
+  p->use_graph = o.use_graph;
+  const int kw = 2 * radius + 1;
+  const int ncoef = ndim == 2 ? kw * kw : kw * kw * kw;
+  p->coeffs.assign(coeffs, coeffs + ncoef);
+  for (double c : p->coeffs)
+    if (!std::isfinite(c)) {
+      delete p;
+      return fail(SPIDER_ERR_INVALID, "coefficients must be finite");
+    }
+  p->grid_bytes = (size_t)p->nz * p->ny * p->nx * dtype_bytes(p->carry);
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+
+  if (engine == SPIDER_ENGINE_DIRECT) {
+    std::vector<char> buf(ncoef * dtype_bytes(p->carry));
+    for (int i = 0; i < ncoef; ++i) {
+      if (p->carry == SPIDER_F64)
+        reinterpret_cast<double*>(buf.data())[i] = p->coeffs[i];
+      else
+        reinterpret_cast<float*>(buf.data())[i] = (float)p->coeffs[i];
+    }
+    e = hipMalloc(&p->d_coeffs, buf.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_coeffs, buf.data(), buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      spider_plan_destroy(p);
+      return hip_fail(e, "coefficient upload");
+    }
+    p->nrows = ndim == 2 ? kw : kw * kw;
+    p->tile_h = o.tile_h ? o.tile_h : auto_tile_h_direct(p);
+  } else {
+    // Offline transformation, one kernel row (line of taps along x) at a time.
+    const int nrows = ndim == 2 ? kw : kw * kw;
+    p->nrows = nrows;
+    std::vector<PackedRow> rows(nrows);
+    std::vector<uint32_t> ipack(((nrows + 1) / 2) * 64, 0u);
+    std::vector<uint32_t> dpack((size_t)nrows * 64 * 8, 0u);
+    uint32_t mask = 0;
+    for (int i = 0; i < nrows; ++i) {
+      const double* row = p->coeffs.data() + (size_t)i * kw;
+      bool nz = false;
+      for (int t = 0; t < kw; ++t) nz |= row[t] != 0.0;
+      if (nz) mask |= 1u << i;
+      std::string err;
+      if (!pack_row(row, radius, p->operand, p->split, &rows[i], &err)) {
+        spider_plan_destroy(p);
+        return fail(SPIDER_ERR_INVALID, "%s", err.c_str());
+      }
+      for (int lane = 0; lane < 64; ++lane) {
+        ipack[(i / 2) * 64 + lane] |= (uint32_t)rows[i].idx[lane] << (16 * (i % 2));
+        std::memcpy(&dpack[((size_t)i * 64 + lane) * 8], &rows[i].dense[lane * 16], 32);
+      }
+    }
+    p->rowmask = mask;
+    std::vector<uint16_t> apack((size_t)nrows * 64 * 8);
+    for (int i = 0; i < nrows; ++i) std::memcpy(&apack[(size_t)i * 64 * 8], rows[i].a, sizeof(rows[i].a));
+    e = hipMalloc(&p->d_apack, apack.size() * 2);
+    if (e == hipSuccess) e = hipMemcpy(p->d_apack, apack.data(), apack.size() * 2, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_ipack, ipack.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(p->d_ipack, ipack.data(), ipack.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_dpack, dpack.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(p->d_dpack, dpack.data(), dpack.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      spider_plan_destroy(p);
+      return hip_fail(e, "operand upload");
+    }
+    p->tile_h = o.tile_h ? o.tile_h : (ndim == 2 ? auto_tile_h_2d(p) : std::min(p->nz, 32));
+    BandGrid& g = p->grid_template;
+    std::memset(&g, 0, sizeof(g));
+    g.nz = p->nz;
+    g.ny = p->ny;
+    g.nx = p->nx;
+    g.seg_h = p->tile_h;
+    g.nstrips = (p->nx + kStripW - 1) / kStripW;
+    g.apack = static_cast<const uint4*>(p->d_apack);
+    g.ipack = static_cast<const uint32_t*>(p->d_ipack);
+    g.dpack = static_cast<const uint4*>(p->d_dpack);
+    g.rowmask = mask;
+    if (ndim == 2) {
+      g.nsegs_y = (p->ny + p->tile_h - 1) / p->tile_h;
+      g.nsegs_z = 1;
+    } else {
+      g.nsegs_y = (p->ny + kRowsY3 - 1) / kRowsY3;
+      g.nsegs_z = (p->nz + p->tile_h - 1) / p->tile_h;
+    }
+    g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
+  }
+  e = hipMalloc(&p->d_scratch, p->grid_bytes);
+  if (e != hipSuccess) {
+    spider_plan_destroy(p);
+    return fail(SPIDER_ERR_OOM, "scratch allocation of %zu bytes failed: %s", p->grid_bytes, hipGetErrorString(e));
+  }
+  *out = p;
+  return SPIDER_OK;
+}
+
+spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps, void* stream) {
+  clear_err();
+  if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
+  if (!in || !out) return fail(SPIDER_ERR_INVALID, "in/out is NULL");
+  if (steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (!p->use_graph || steps < 2) return enqueue_steps(p, in, out, steps, s);
+  // Replay a graph of the whole time loop, captured once per (in, out, steps).
+  auto key = std::make_tuple(in, (const void*)out, steps);
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    if (!p->cap_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
+    hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    spider_status st = enqueue_steps(p, in, out, steps, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (st != SPIDER_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (p->graphs.size() >= 64) {  // bound the cache
+      hipGraphExecDestroy(p->graphs.begin()->second);
+      p->graphs.erase(p->graphs.begin());
+    }
+    it = p->graphs.emplace(key, exec).first;
+  }
+  hipError_t e = hipGraphLaunch(it->second, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return SPIDER_OK;
+}
+
+spider_status spider_plan_destroy(spider_plan_t p) {
+  if (!p) return SPIDER_OK;
+  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  if (p->d_apack) hipFree(p->d_apack);
+  if (p->d_ipack) hipFree(p->d_ipack);
+  if (p->d_dpack) hipFree(p->d_dpack);
+  if (p->d_coeffs) hipFree(p->d_coeffs);
+  if (p->d_scratch) hipFree(p->d_scratch);
+  delete p;
+  return SPIDER_OK;
+}
+
+spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* tile_h, int* nrows_nonzero,
+                               size_t* scratch_bytes) {
+  clear_err();
+  if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
+  if (engine) *engine = p->engine;
+  if (carry) *carry = p->carry;
+  if (tile_h) *tile_h = p->tile_h;
+  if (nrows_nonzero) {
+    int n = 0;
+    if (p->engine == SPIDER_ENGINE_DIRECT) {
+      n = p->nrows;
+    } else {
+      for (int i = 0; i < p->nrows; ++i) n += (p->rowmask >> i) & 1u;
+    }
+    *nrows_nonzero = n;
+  }
+  if (scratch_bytes) *scratch_bytes = p->grid_bytes;
+  return SPIDER_OK;
+}
+
+// ------------------------------------------------------------------ host introspection
+
+spider_status spider_gather_positions(int pos[32]) {
+  clear_err();
+  if (!pos) return fail(SPIDER_ERR_INVALID, "pos is NULL");
+  gather_positions(pos);
+  return SPIDER_OK;
+}
+
+spider_status spider_swap_columns(int L, int granularity, int* perm) {
+  clear_err();
+  if (!swap_columns(L, granularity, perm)) return fail(SPIDER_ERR_INVALID, "bad L / granularity");
+  return SPIDER_OK;
+}
+
+spider_status spider_compress_24(const double* m, int rows, int cols, double* vals, uint8_t* meta) {
+  clear_err();
+  if (!compress_24(m, rows, cols, vals, meta)) return fail(SPIDER_ERR_INVALID, "matrix is not 2:4 or bad sizes");
+  return SPIDER_OK;
+}
+
+spider_status spider_pack_row(const double* row, int radius, int operand, int split, uint16_t* a_bits, uint16_t* idx,
+                              uint16_t* dense_bits) {
+  clear_err();
+  if (!row || !a_bits || !idx) return fail(SPIDER_ERR_INVALID, "NULL argument");
+  PackedRow pr;
+  std::string err;
+  if (!pack_row(row, radius, operand, split, &pr, &err)) return fail(SPIDER_ERR_INVALID, "%s", err.c_str());
+  std::memcpy(a_bits, pr.a, sizeof(pr.a));
+  std::memcpy(idx, pr.idx, sizeof(pr.idx));
+  if (dense_bits) std::memcpy(dense_bits, pr.dense, sizeof(pr.dense));
+  return SPIDER_OK;
+}
+
+}  // extern "C"
