@@ -7,7 +7,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/spider.h"
+#include "spider.h"
 #include "kernels.h"
 
 struct spider_plan_s {
@@ -24,6 +24,7 @@ struct spider_plan_s {
   std::vector<double> coeffs;
   int nrows = 0;          // kernel rows (lines of taps along x)
   uint32_t rowmask = 0;   // rows with a non-zero tap
+  bool has_zero_tap = false;
   void* d_apack = nullptr;
   void* d_ipack = nullptr;
   void* d_dpack = nullptr;

@@ -125,10 +125,9 @@ __device__ __forceinline__ uint32_t out_voffset(int x0, int lane) {
   return (uint32_t)((x0 + 16 * (lane & 15) + 4 * (lane >> 4)) * 2);
 }
 
-// Store 4 outputs; the line resource drops whatever lies outside [0, nx).
-template <int OP, bool ALIGNED>
-__device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, uint32_t voff, f32x4 a) {
-  const uint2 w = pack_out<OP>(a);
+// Store 4 packed 16-bit outputs; the line resource drops whatever lies outside [0, nx).
+template <bool ALIGNED>
+__device__ __forceinline__ void store_packed(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint2 w) {
   if constexpr (ALIGNED) {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64((u32x2){w.x, w.y}, rs, voff, 0, 0);
@@ -138,6 +137,11 @@ __device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, uint32_t vo
     __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w.y & 0xffff), rs, voff + 4, 0, 0);
     __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w.y >> 16), rs, voff + 6, 0, 0);
   }
+}
+
+template <int OP, bool ALIGNED>
+__device__ __forceinline__ void store_out(__amdgpu_buffer_rsrc_t rs, uint32_t voff, f32x4 a) {
+  store_packed<ALIGNED>(rs, voff, pack_out<OP>(a));
 }
 
 // One matrix instruction: acc += A(kernel row) x B(input line).

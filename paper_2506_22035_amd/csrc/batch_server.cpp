@@ -1,7 +1,7 @@
 // Batched apply and the continuous-batching server.
 #include <hip/hip_runtime.h>
 
-#include "../../include/spider.h"
+#include "spider.h"
 #include "api_internal.h"
 
 using namespace spider_impl;

@@ -37,14 +37,16 @@ hipError_t launch_band3d(int r, int operand, int engine, const BandGrid* grids_d
 
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
+int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);
 
 // Output rows per 3-D wave along y (accumulator block height).
 constexpr int kRowsY3 = 4;
 
 // Plain direct-sum engine (fp32 / fp64 carry).  coeffs_dev holds (2r+1)^ndim
-// taps in the carry dtype.  dtype: 0 = f64, 1 = f32.
-hipError_t launch_direct(int ndim, int r, int dtype, const void* in, void* out, int nz, int ny, int nx,
-                         const void* coeffs_dev, int seg_h, hipStream_t s);
+// taps in the carry dtype.  dtype: 0 = f64, 1 = f32.  skip_zero_taps selects the
+// variant that branches over zero taps (star shapes) instead of multiplying them.
+hipError_t launch_direct(int ndim, int r, int dtype, bool skip_zero_taps, const void* in, void* out, int nz, int ny,
+                         int nx, const void* coeffs_dev, int seg_h, hipStream_t s);
 
 // Rows of the 2-D band wave: stride between wave strips along x.
 constexpr int kStripW = 256;

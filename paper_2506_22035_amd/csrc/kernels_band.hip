@@ -80,11 +80,23 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
   f32x4 acc[RR];
 #pragma unroll
   for (int s = 0; s < RR; ++s) acc[s] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  // Output lines finished in a body are stored at the start of the next body,
+  // before that body's loads are issued, so the wait for staged rows at a body
+  // start only covers memory operations issued a whole body earlier.
+  uint2 done[U];
 
   for (int jb = 0; jb < nin; jb += U) {
     wave_lds_sync();  // previous body's gathers are issued before its LDS rows are reused
 #pragma unroll
     for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    if (jb > 0) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i = jb - U + q - 2 * R;
+        const bool ovalid = i >= 0 && i < hrows;
+        store_packed<ALIGNED>(line_rsrc(g.out, (size_t)(y0 + i) * nx, nx, ovalid, 2), ovoff, done[q]);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int jn = jb + U + q;
@@ -95,11 +107,10 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int j = jb + q;
       const uint32_t* lrow = lds + q * kLdsRowDw;
       const u32x4 b = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
-      // Input row j feeds output row i = j - a through kernel row a; its accumulator
-      // slot is (j - a) mod RR = (q - a) mod RR because U is a multiple of RR.
+      // Input row j = jb + q feeds output row i = j - a through kernel row a; its
+      // accumulator slot is (j - a) mod RR = (q - a) mod RR because U is a multiple of RR.
 #pragma unroll
       for (int a = 0; a < RR; ++a) {
         const int slot = ((q - a) % RR + RR) % RR;
@@ -108,18 +119,23 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
         else
           acc[slot] = band_mma<OP, ENG, 0>(acc[slot], A[a], Dh[a], Dl[a], I[a / 2], b);
       }
-      // Output row j - 2r has received its last kernel row: store it, recycle the slot.
-      const int i = j - 2 * R;
+      // Output row j - 2r has received its last kernel row; recycle its slot.
       const int fs = (q + 1) % RR;
-      const bool ovalid = i >= 0 && i < hrows;
-      store_out<OP, ALIGNED>(line_rsrc(g.out, (size_t)(y0 + i) * nx, nx, ovalid, 2), ovoff, acc[fs]);
+      done[q] = pack_out<OP>(acc[fs]);
       acc[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int i = nin - U + q - 2 * R;
+    const bool ovalid = i >= 0 && i < hrows;
+    store_packed<ALIGNED>(line_rsrc(g.out, (size_t)(y0 + i) * nx, nx, ovalid, 2), ovoff, done[q]);
   }
 }
 
 template <int R, int OP, int ENG, bool ALIGNED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 3 ? 4 : 2))) void band2d_kernel(BandGrid g) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && ENG == 1) ? 4 : (R <= 3 ? 3 : 2))))
+void band2d_kernel(BandGrid g) {
   constexpr int RR = 2 * R + 1;
   constexpr int U = (RR >= 5) ? RR : 2 * RR;
   __shared__ uint32_t lds[U * kLdsRowDw + kLdsSpareDw];
@@ -157,8 +173,173 @@ hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* /*grids
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_band3d(int, int, int, const BandGrid*, const BandGrid*, int, hipStream_t) {
-  return hipErrorNotSupported;
+// ----------------------------------------------------------------------------- 3-D
+// Kernel row (dz, dy) is packed as row dz * (2r+1) + dy.  MASK has bit
+// dz * (2r+1) + dy set for the rows that are multiplied (compile time, so star
+// shapes skip their all-zero rows without branches).
+
+template <int R>
+constexpr uint32_t box_mask3() {
+  return (1u << ((2 * R + 1) * (2 * R + 1))) - 1u;
+}
+template <int R>
+constexpr uint32_t star_mask3() {
+  // rows with a tap on a coordinate axis: dz == R or dy == R
+  uint32_t m = 0;
+  for (int dz = 0; dz <= 2 * R; ++dz)
+    for (int dy = 0; dy <= 2 * R; ++dy)
+      if (dz == R || dy == R) m |= 1u << (dz * (2 * R + 1) + dy);
+  return m;
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, uint32_t MASK>
+__device__ __forceinline__ void band3d_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int NR = RR * RR;          // kernel rows
+  constexpr int YB = kRowsY3;          // output lines per plane
+  constexpr int NL = YB + 2 * R;       // input lines per plane
+  const int lane = threadIdx.x;
+  int t = w;
+  const int strip = t % g.nstrips;
+  t /= g.nstrips;
+  const int sy = t % g.nsegs_y, sz = t / g.nsegs_y;
+  const int x0 = strip * kStripW, yb0 = sy * YB, z0 = sz * g.seg_h;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int hz = min(g.seg_h, nz - z0);
+  const int npl = ((hz + 2 * R + RR - 1) / RR) * RR;  // planes streamed, padded to RR
+
+  u32x4 A[NR], Dh[NR], Dl[NR];
+  uint32_t I[(NR + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < NR; ++a) {
+    if constexpr (ENG == 1) {
+      A[a] = (MASK >> a & 1u) ? reinterpret_cast<const u32x4*>(g.apack)[a * 64 + lane] : (u32x4){0, 0, 0, 0};
+      Dh[a] = Dl[a] = (u32x4){0, 0, 0, 0};
+    } else {
+      A[a] = (u32x4){0, 0, 0, 0};
+      Dh[a] = (MASK >> a & 1u) ? reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 0] : (u32x4){0, 0, 0, 0};
+      Dl[a] = (MASK >> a & 1u) ? reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 1] : (u32x4){0, 0, 0, 0};
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < (NR + 1) / 2; ++a) I[a] = (ENG == 1) ? g.ipack[a * 64 + lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const uint32_t lvoff = chunk_voffset(x0, lane);
+  const uint32_t ovoff = out_voffset(x0, lane);
+  const int lw = chunk_lds_offset(lane, NL * kLdsRowDw);
+  const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
+
+  // plane pj is z = z0 - R + pj; stg holds its NL lines (y = yb0 - R + l)
+  u32x4 stg[NL];
+  auto stage = [&](int pj) {
+    const int z = z0 - R + pj;
+    const bool zvalid = pj < hz + 2 * R && z >= 0 && z < nz;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int y = yb0 - R + l;
+      const bool valid = zvalid && y >= 0 && y < ny;
+      stg[l] = load_chunk<ALIGNED>(line_rsrc(g.in, ((size_t)z * ny + y) * nx, nx, valid, 2), lvoff);
+    }
+  };
+  stage(0);
+  f32x4 acc[RR][YB];
+#pragma unroll
+  for (int s = 0; s < RR; ++s)
+#pragma unroll
+    for (int b = 0; b < YB; ++b) acc[s][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  uint2 done[YB];
+  int done_plane = -1;  // plane index (within the segment) held in `done`, -1 = none
+
+  for (int pb = 0; pb < npl; pb += RR) {
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+      const int pj = pb + q;
+      wave_lds_sync();
+#pragma unroll
+      for (int l = 0; l < NL; ++l) store_chunk_lds(lds, lw + l * lstride, stg[l]);
+      if (done_plane >= 0) {
+#pragma unroll
+        for (int b = 0; b < YB; ++b) {
+          const int y = yb0 + b;
+          const bool ov = done_plane < hz && y < ny;
+          store_packed<ALIGNED>(line_rsrc(g.out, ((size_t)(z0 + done_plane) * ny + y) * nx, nx, ov, 2), ovoff,
+                                done[b]);
+        }
+      }
+      stage(pj + 1);
+      wave_lds_sync();
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        const uint32_t* lrow = lds + l * kLdsRowDw;
+        const u32x4 bv = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+#pragma unroll
+        for (int dz = 0; dz < RR; ++dz) {
+          const int slot = ((q - dz) % RR + RR) % RR;  // output plane pj - dz
+#pragma unroll
+          for (int b = 0; b < YB; ++b) {
+            const int dy = l - b;  // input line yb0 - R + l feeds output line yb0 + b
+            if (dy < 0 || dy >= RR) continue;
+            const int a = dz * RR + dy;
+            if (!(MASK >> a & 1u)) continue;
+            if (a & 1)
+              acc[slot][b] = band_mma<OP, ENG, 1>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bv);
+            else
+              acc[slot][b] = band_mma<OP, ENG, 0>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bv);
+          }
+        }
+      }
+      // output plane pj - 2R is complete
+      const int fs = (q + 1) % RR;
+#pragma unroll
+      for (int b = 0; b < YB; ++b) {
+        done[b] = pack_out<OP>(acc[fs][b]);
+        acc[fs][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      }
+      done_plane = pj - 2 * R;
+    }
+  }
+  if (done_plane >= 0) {
+#pragma unroll
+    for (int b = 0; b < YB; ++b) {
+      const int y = yb0 + b;
+      const bool ov = done_plane < hz && y < ny;
+      store_packed<ALIGNED>(line_rsrc(g.out, ((size_t)(z0 + done_plane) * ny + y) * nx, nx, ov, 2), ovoff, done[b]);
+    }
+  }
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, uint32_t MASK>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3 : 2))) void band3d_kernel(BandGrid g) {
+  constexpr int NL = kRowsY3 + 2 * R;
+  __shared__ uint32_t lds[NL * kLdsRowDw + kLdsSpareDw];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band3d_body<R, OP, ENG, ALIGNED, MASK>(g, w, lds);
+}
+
+template <int OP, int ENG, bool AL>
+static hipError_t dispatch3d(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  if (r != 1) return hipErrorInvalidValue;
+  if ((g.rowmask & ~star_mask3<1>()) == 0)  // every non-zero row lies on the star
+    hipLaunchKernelGGL((band3d_kernel<1, OP, ENG, AL, star_mask3<1>()>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((band3d_kernel<1, OP, ENG, AL, box_mask3<1>()>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_band3d(int r, int operand, int engine, const BandGrid* /*grids_dev*/, const BandGrid* grids_host,
+                         int n, hipStream_t s) {
+  if (n != 1) return hipErrorInvalidValue;
+  const BandGrid& g = grids_host[0];
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2 && engine == 1) return al ? dispatch3d<2, 1, true>(r, g, s) : dispatch3d<2, 1, false>(r, g, s);
+  if (operand == 2 && engine == 2) return al ? dispatch3d<2, 2, true>(r, g, s) : dispatch3d<2, 2, false>(r, g, s);
+  if (operand == 3 && engine == 1) return al ? dispatch3d<3, 1, true>(r, g, s) : dispatch3d<3, 1, false>(r, g, s);
+  if (operand == 3 && engine == 2) return al ? dispatch3d<3, 2, true>(r, g, s) : dispatch3d<3, 2, false>(r, g, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace spider_impl
@@ -181,6 +362,26 @@ static int occ2d(int r) {
     default: break;
   }
   return e == hipSuccess ? nb : 0;
+}
+
+template <int OP, int ENG, bool AL>
+static int occ3d(int r, uint32_t rowmask) {
+  int nb = 0;
+  if (r != 1) return 0;
+  hipError_t e;
+  if ((rowmask & ~star_mask3<1>()) == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band3d_kernel<1, OP, ENG, AL, star_mask3<1>()>, 64, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band3d_kernel<1, OP, ENG, AL, box_mask3<1>()>, 64, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask) {
+  if (operand == 2 && engine == 1) return aligned ? occ3d<2, 1, true>(r, rowmask) : occ3d<2, 1, false>(r, rowmask);
+  if (operand == 2 && engine == 2) return aligned ? occ3d<2, 2, true>(r, rowmask) : occ3d<2, 2, false>(r, rowmask);
+  if (operand == 3 && engine == 1) return aligned ? occ3d<3, 1, true>(r, rowmask) : occ3d<3, 1, false>(r, rowmask);
+  if (operand == 3 && engine == 2) return aligned ? occ3d<3, 2, true>(r, rowmask) : occ3d<3, 2, false>(r, rowmask);
+  return 0;
 }
 
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned) {

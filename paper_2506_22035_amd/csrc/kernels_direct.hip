@@ -30,6 +30,15 @@ __device__ __forceinline__ void wave_sync() {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Fused multiply-add in the carry type (fp32 stays fp32).
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
 // Geometry of a staged line: x in [x0 - LEAD, x0 + SW + LEAD) with LEAD = 4 ceil(r/4)
 // and strip width SW = 256 - 2 LEAD, so a line is exactly 256 values (one 16-byte
 // load per lane for fp32, two for fp64).  Lanes with 4 lane >= SW compute nothing.
@@ -134,7 +143,7 @@ __device__ __forceinline__ void store_out4(__amdgpu_buffer_rsrc_t rs, int x0, in
 // feeds it through kernel row a = 2R - m.  After line j, acc[0] is complete and the
 // window shifts by one line.  Lines are staged two ahead.
 
-template <typename T, int R>
+template <typename T, int R, bool SKIPZ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void direct2d_kernel(
     const T* __restrict__ in, T* __restrict__ out, int ny, int nx, const T* __restrict__ w, int seg_h, int nstrips) {
   using L = Line<T, R>;
@@ -180,9 +189,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
 #pragma unroll
         for (int t = 0; t < RR; ++t) {
           const T c = w[a * RR + t];
-          if (c != T(0)) {
+          if (!SKIPZ || c != T(0)) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc[m][k] = __builtin_fma(c, v[k + t - R + L::LEAD], acc[m][k]);
+            for (int k = 0; k < 4; ++k) acc[m][k] = fma_t<T>(c, v[k + t - R + L::LEAD], acc[m][k]);
           }
         }
       }
@@ -205,7 +214,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
 // streams input planes (kRowsY3 + 2R lines each), staged one plane ahead.
 // acc[m][b] holds output line (plane p - 2R + m, y = yb0 + b) while plane p is applied.
 
-template <typename T, int R>
+template <typename T, int R, bool SKIPZ>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void direct3d_kernel(
     const T* __restrict__ in, T* __restrict__ out, int nz, int ny, int nx, const T* __restrict__ w, int seg_h,
     int nstrips, int nsegy) {
@@ -262,9 +271,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void di
 #pragma unroll
           for (int t = 0; t < RR; ++t) {
             const T c = w[(dz * RR + dy) * RR + t];
-            if (c != T(0)) {
+            if (!SKIPZ || c != T(0)) {
 #pragma unroll
-              for (int k = 0; k < 4; ++k) acc[m][b][k] = __builtin_fma(c, v[k + t - R + L::LEAD], acc[m][b][k]);
+              for (int k = 0; k < 4; ++k) acc[m][b][k] = fma_t<T>(c, v[k + t - R + L::LEAD], acc[m][b][k]);
             }
           }
         }
@@ -294,7 +303,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void di
 
 // ------------------------------------------------------------------ dispatch
 
-template <typename T>
+template <typename T, bool SKIPZ>
 static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, int nz, int ny, int nx,
                                   const void* w, int seg_h, hipStream_t s) {
   const int sw = 256 - 2 * 4 * ((r + 3) / 4);
@@ -307,7 +316,7 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
     const dim3 grid(nstrips * nseg), block(64);
     switch (r) {
 #define SPIDER_D2(RV) \
-  case RV: hipLaunchKernelGGL((direct2d_kernel<T, RV>), grid, block, 0, s, pin, pout, ny, nx, pw, seg_h, nstrips); break;
+  case RV: hipLaunchKernelGGL((direct2d_kernel<T, RV, SKIPZ>), grid, block, 0, s, pin, pout, ny, nx, pw, seg_h, nstrips); break;
       SPIDER_D2(1) SPIDER_D2(2) SPIDER_D2(3) SPIDER_D2(4) SPIDER_D2(5) SPIDER_D2(6) SPIDER_D2(7)
 #undef SPIDER_D2
       default: return hipErrorInvalidValue;
@@ -319,7 +328,7 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
     switch (r) {
 #define SPIDER_D3(RV)                                                                                                \
   case RV:                                                                                                           \
-    hipLaunchKernelGGL((direct3d_kernel<T, RV>), grid, block, 0, s, pin, pout, nz, ny, nx, pw, seg_h, nstrips, nsegy); \
+    hipLaunchKernelGGL((direct3d_kernel<T, RV, SKIPZ>), grid, block, 0, s, pin, pout, nz, ny, nx, pw, seg_h, nstrips, nsegy); \
     break;
       SPIDER_D3(1) SPIDER_D3(2)
 #undef SPIDER_D3
@@ -329,10 +338,14 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
   return hipGetLastError();
 }
 
-hipError_t launch_direct(int ndim, int r, int dtype, const void* in, void* out, int nz, int ny, int nx,
-                         const void* coeffs_dev, int seg_h, hipStream_t s) {
-  if (dtype == 0) return direct_dispatch<double>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
-  if (dtype == 1) return direct_dispatch<float>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
+hipError_t launch_direct(int ndim, int r, int dtype, bool skip_zero_taps, const void* in, void* out, int nz, int ny,
+                         int nx, const void* coeffs_dev, int seg_h, hipStream_t s) {
+  if (dtype == 0)
+    return skip_zero_taps ? direct_dispatch<double, true>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s)
+                          : direct_dispatch<double, false>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
+  if (dtype == 1)
+    return skip_zero_taps ? direct_dispatch<float, true>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s)
+                          : direct_dispatch<float, false>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
   return hipErrorInvalidValue;
 }
 

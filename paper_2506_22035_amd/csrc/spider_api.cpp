@@ -14,7 +14,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/spider.h"
+#include "spider.h"
 #include "api_internal.h"
 #include "kernels.h"
 #include "planner.h"
@@ -64,9 +64,30 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
   const long long nstrips = (p->nx + kStripW - 1) / kStripW;
-  long long h = (p->ny * nstrips + slots - 1) / slots;
+  // segments per strip that keep every wave resident: ceil(ny / h) * nstrips <= slots
+  const long long segs = std::max<long long>(1, slots / nstrips);
+  long long h = (p->ny + segs - 1) / segs;
   h = std::max<long long>(h, 16);
   h = std::min<long long>(h, p->ny);
+  return (int)h;
+}
+
+// Planes per wave segment of the 3-D band kernel: one resident round over
+// (strip, 4-line y block, z segment) work units, at least 8 planes deep.
+static int auto_tile_h_3d(const spider_plan_s* p) {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  int per_cu = band3d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0, p->rowmask);
+  if (per_cu <= 0) per_cu = 8;
+  const long long slots = (long long)ncu * per_cu;
+  const long long cols = (long long)((p->nx + kStripW - 1) / kStripW) * ((p->ny + kRowsY3 - 1) / kRowsY3);
+  const long long segs = std::max<long long>(1, slots / cols);
+  long long h = (p->nz + segs - 1) / segs;
+  h = std::max<long long>(h, 8);
+  h = std::min<long long>(h, p->nz);
   return (int)h;
 }
 
@@ -79,8 +100,8 @@ static int auto_tile_h_direct(const spider_plan_s* p) {
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
   hipError_t e;
   if (p->engine == SPIDER_ENGINE_DIRECT) {
-    e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, src, dst, p->nz, p->ny, p->nx, p->d_coeffs,
-                      p->tile_h, s);
+    e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, p->has_zero_tap, src, dst, p->nz, p->ny, p->nx,
+                      p->d_coeffs, p->tile_h, s);
   } else if (p->ndim == 2) {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -222,6 +243,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       return hip_fail(e, "coefficient upload");
     }
     p->nrows = ndim == 2 ? kw : kw * kw;
+    p->has_zero_tap = false;
+    for (double c : p->coeffs) p->has_zero_tap |= (c == 0.0);
     p->tile_h = o.tile_h ? o.tile_h : auto_tile_h_direct(p);
   } else {
     // Offline transformation, one kernel row (line of taps along x) at a time.
@@ -259,7 +282,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       spider_plan_destroy(p);
       return hip_fail(e, "operand upload");
     }
-    p->tile_h = o.tile_h ? o.tile_h : (ndim == 2 ? auto_tile_h_2d(p) : std::min(p->nz, 32));
+    p->tile_h = o.tile_h ? o.tile_h : (ndim == 2 ? auto_tile_h_2d(p) : auto_tile_h_3d(p));
     BandGrid& g = p->grid_template;
     std::memset(&g, 0, sizeof(g));
     g.nz = p->nz;

@@ -131,7 +131,8 @@ def grid_sinusoids(shape, seed, dtype=np.float32, nwaves=8, noise=0.01):
     f(y, x) = (1/nwaves) sum_k a_k sin(2 pi (kx_k x / Nx + ky_k y / Ny) + phi_k)
               + noise * U[-1, 1),
     a_k ~ U[0.5, 1], kx_k, ky_k ~ U{1..16}, phi_k ~ U[0, 2 pi).
-    Built row-block by row-block so 10240^2 grids need no fp64 full-size temporaries.
+    Evaluated as sin(u + v) = sin u cos v + cos u sin v, i.e. one (Ny x 2n) @ (2n x Nx)
+    product, row block by row block.
     """
     ny, nx = shape
     rng = np.random.default_rng(seed)
@@ -139,16 +140,16 @@ def grid_sinusoids(shape, seed, dtype=np.float32, nwaves=8, noise=0.01):
     kx = rng.integers(1, 17, nwaves)
     ky = rng.integers(1, 17, nwaves)
     ph = rng.uniform(0.0, 2.0 * np.pi, nwaves)
-    xs = np.arange(nx, dtype=np.float64) / nx
+    u = 2.0 * np.pi * kx[:, None] * (np.arange(nx, dtype=np.float64) / nx)[None, :] + ph[:, None]  # n x Nx
+    right = np.concatenate([np.sin(u), np.cos(u)], axis=0)                                         # 2n x Nx
     out = np.empty((ny, nx), dtype=dtype)
     nrng = np.random.default_rng(seed + 1_000_003)
-    blk = 512
+    blk = 1024
     for y0 in range(0, ny, blk):
-        ys = np.arange(y0, min(ny, y0 + blk), dtype=np.float64)[:, None] / ny
-        f = np.zeros((ys.shape[0], nx), dtype=np.float64)
-        for k in range(nwaves):
-            f += a[k] * np.sin(2.0 * np.pi * (kx[k] * xs[None, :] + ky[k] * ys) + ph[k])
-        f /= nwaves
+        ys = np.arange(y0, min(ny, y0 + blk), dtype=np.float64) / ny
+        v = 2.0 * np.pi * ys[:, None] * ky[None, :]                                                 # b x n
+        left = np.concatenate([a * np.cos(v), a * np.sin(v)], axis=1) / nwaves                       # b x 2n
+        f = left @ right
         f += noise * nrng.uniform(-1.0, 1.0, f.shape)
         out[y0:y0 + ys.shape[0]] = f.astype(dtype)
     return out

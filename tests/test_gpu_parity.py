@@ -199,3 +199,75 @@ def test_full_size_box2d49p_sampled(oracle_mod, carry):
     tr, tm = TOL[(carry, 2)]
     assert rms <= tr and mx <= tm
     assert np.isfinite(got).all()
+
+
+# ------------------------------------------------------------------ 3-D
+
+SHAPES_3D = [(9, 10, 300), (5, 7, 257), (1, 1, 1), (20, 9, 520), (3, 4, 8)]
+
+
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("kind", ["box", "star"])
+@pytest.mark.parametrize("shape", SHAPES_3D)
+def test_integer_exact_3d_f16(oracle_mod, engine, kind, shape):
+    w = si.integer_coeffs(3, 1, -4, 4, 50, kind)
+    x = si.grid_integer(shape, -8, 8, 60 + shape[2])
+    xd, x64 = to_dev(x, "f16")
+    plan = sp.Plan(w, shape, carry="f16", engine=engine)
+    got = run(plan, xd, 1)
+    ref = oracle_mod.apply(w, x64, 1)
+    assert np.array_equal(got, ref), np.argwhere(got != ref)[:5]
+
+
+def test_integer_exact_3d_multistep_and_tiles(oracle_mod):
+    shape = (23, 13, 264)
+    w = si.integer_coeffs(3, 1, -1, 1, 3, "box")
+    x = si.grid_integer(shape, -1, 1, 4)   # 2 steps: |v| <= 27 * 27 = 729, exact in fp16
+    xd, x64 = to_dev(x, "f16")
+    ref = oracle_mod.apply(w, x64, 2)
+    for th in (0, 1, 4, 7, 100):
+        plan = sp.Plan(w, shape, carry="f16", tile_h=th)
+        assert np.array_equal(run(plan, xd, 2), ref), th
+
+
+@pytest.mark.parametrize("carry", ["f16", "bf16"])
+@pytest.mark.parametrize("name", ["box3d27p_512", "heat3d_256"])
+def test_workload_tolerance_3d(oracle_mod, carry, name):
+    wl = si.workload(name, small=True)
+    xd, x64 = to_dev(wl["make_grid"](), carry)
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=carry)
+    got = run(plan, xd, wl["steps"])
+    rms, mx = rel_errors(got, oracle_mod.apply(wl["coeffs"], x64, wl["steps"]))
+    tr, tm = TOL[(carry, 2)]
+    assert rms <= tr and mx <= tm, (rms, mx)
+
+
+def test_direct_3d_f32(oracle_mod):
+    wl = si.workload("box3d27p_512", small=True)
+    xd, x64 = to_dev(wl["make_grid"](), "f32")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32")
+    got = run(plan, xd, wl["steps"])
+    rms, mx = rel_errors(got, oracle_mod.apply(wl["coeffs"], x64, wl["steps"]))
+    assert rms <= 1e-5 and mx <= 1e-5
+
+
+def test_full_size_box3d27p_sampled(oracle_mod):
+    # Box-3D27P at 512^3, 20 steps; sampled points against the oracle on their cones
+    wl = si.workload("box3d27p_512")
+    xd, x64 = to_dev(wl["make_grid"](), "f16")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+    got = run(plan, xd, wl["steps"])
+    T = wl["steps"]
+    n = 512
+    rng = np.random.default_rng(1)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, 255, 511)] + [tuple(int(v) for v in rng.integers(0, n, 3))
+                                                                for _ in range(6)]
+    ref, g = [], []
+    for p in pts:
+        lo = [max(0, c - T) for c in p]
+        hi = [min(n, c + T + 1) for c in p]
+        sub = oracle_mod.apply(wl["coeffs"], x64[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]], T)
+        ref.append(sub[p[0] - lo[0], p[1] - lo[1], p[2] - lo[2]])
+        g.append(got[p])
+    rms, mx = rel_errors(np.array(g), np.array(ref))
+    assert rms <= 2e-3 and mx <= 1e-2, (rms, mx)
