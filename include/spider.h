@@ -67,7 +67,10 @@ typedef struct {
     int tile_h;    /* output rows per wavefront segment, 0 = chosen by the autotuner */
     int use_graph; /* 1 = capture each (in, out, steps) time loop once as a hipGraph and
                       replay it (default), 0 = launch every step */
-    int reserved[3];
+    int autotune;  /* 1 = when tile_h is 0, time candidate segment heights on the device at
+                      plan time and keep the fastest (results cached per shape, radius,
+                      engine and dtype for the life of the process); 0 = occupancy heuristic */
+    int reserved[2];
 } spider_opts;
 
 typedef struct spider_plan_s* spider_plan_t;

@@ -44,4 +44,6 @@ void clear_err();
 size_t dtype_bytes(int dt);
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
+// Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).
+spider_status autotune_tile(spider_plan_s* p);
 }  // namespace spider_impl

@@ -1,0 +1,110 @@
+// Autotuner for the segment height of the band and direct engines.
+//
+// The paper fixes its tile sizes by a predefined strategy (Sec. 4.2); on
+// MI355X the best height depends on how many waves stay resident, on the halo
+// share and on cache reuse between neighbouring segments, and it is not
+// monotonic, so it is measured: every candidate runs a few time steps on the
+// plan's own scratch memory and the fastest is kept.  Results are cached for
+// the life of the process, keyed by everything that changes the kernel's cost.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "api_internal.h"
+#include "kernels.h"
+
+namespace spider_impl {
+
+namespace {
+using Key = std::tuple<int, int, int, int, int, int, int, uint32_t, bool>;
+std::mutex g_mu;
+std::map<Key, int> g_cache;
+
+Key key_of(const spider_plan_s* p) {
+  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine, p->rowmask, p->has_zero_tap);
+}
+
+void set_tile(spider_plan_s* p, int h) {
+  p->tile_h = h;
+  BandGrid& g = p->grid_template;
+  g.seg_h = h;
+  if (p->engine != SPIDER_ENGINE_DIRECT) {
+    if (p->ndim == 2) {
+      g.nsegs_y = (p->ny + h - 1) / h;
+      g.nsegs_z = 1;
+    } else {
+      g.nsegs_z = (p->nz + h - 1) / h;
+    }
+    g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
+  }
+}
+}  // namespace
+
+// Candidate heights around the heuristic choice `h0` for an extent `n`.
+static std::vector<int> candidates(int h0, int n) {
+  std::set<int> c;
+  for (int v : {h0, (h0 + 1) / 2, (h0 + 2) / 3, 2 * h0, 8, 16, 32, 64, 96, 128, 192})
+    if (v >= 1 && v <= n) c.insert(v);
+  if (c.empty()) c.insert(std::max(1, std::min(h0, n)));
+  return std::vector<int>(c.begin(), c.end());
+}
+
+spider_status autotune_tile(spider_plan_s* p) {
+  const Key k = key_of(p);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(k);
+    if (it != g_cache.end()) {
+      set_tile(p, it->second);
+      return SPIDER_OK;
+    }
+  }
+  const int n = p->ndim == 3 ? p->nz : p->ny;
+  const std::vector<int> cand = candidates(p->tile_h, n);
+  void* tmp = nullptr;
+  hipError_t e = hipMalloc(&tmp, p->grid_bytes);
+  if (e != hipSuccess) return SPIDER_OK;  // keep the heuristic height when memory is short
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemsetAsync(p->d_scratch, 0, p->grid_bytes, s);
+  if (e == hipSuccess) e = hipMemsetAsync(tmp, 0, p->grid_bytes, s);
+  int best = p->tile_h;
+  float best_ms = 1e30f;
+  const int reps = 4;
+  for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+    set_tile(p, cand[i]);
+    if (launch_step(p, p->d_scratch, tmp, s) != SPIDER_OK) break;  // warm-up
+    e = hipEventRecord(e0, s);
+    for (int r = 0; e == hipSuccess && r < reps; ++r) {
+      if (launch_step(p, (r & 1) ? tmp : p->d_scratch, (r & 1) ? p->d_scratch : tmp, s) != SPIDER_OK) e = hipErrorUnknown;
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = cand[i];
+    }
+  }
+  if (s) hipStreamSynchronize(s);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (s) hipStreamDestroy(s);
+  hipFree(tmp);
+  set_tile(p, best);
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[k] = best;
+  return SPIDER_OK;
+}
+
+}  // namespace spider_impl

@@ -1,10 +1,369 @@
-// Batched apply and the continuous-batching server.
+// Batched time loop over many grids and the continuous-batching server.
+//
+// Batching is not in the paper (it evaluates one grid at a time); it serves
+// many grids of uneven size and stencil shape with one persistent launch per
+// time step, every workgroup pulling (grid, strip, segment) work units from a
+// device counter.  The server admits requests by device footprint and free
+// slots, advances all admitted requests together in rounds of batched steps,
+// and lets requests that arrive meanwhile join at the next round.
 #include <hip/hip_runtime.h>
 
-#include "spider.h"
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "api_internal.h"
+#include "kernels.h"
+#include "spider.h"
 
 using namespace spider_impl;
+
+namespace spider_impl {
+
+struct BatchItem {
+  spider_plan_s* plan;
+  const void* in;
+  void* out;
+  void* scratch;
+  int steps;
+};
+
+// Device and pinned host buffers holding the per-step descriptors of one
+// batched time loop; reused across calls once the previous use has completed.
+struct BatchArena {
+  char* host = nullptr;  // pinned staging
+  char* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  std::mutex mu;
+
+  ~BatchArena() { release(); }
+  void release() {
+    if (done) {
+      hipEventSynchronize(done);
+      hipEventDestroy(done);
+      done = nullptr;
+    }
+    if (host) hipHostFree(host);
+    if (dev) hipFree(dev);
+    host = nullptr;
+    dev = nullptr;
+    cap = 0;
+  }
+  hipError_t reserve(size_t bytes) {
+    if (pending && done) {
+      hipError_t e = hipEventSynchronize(done);
+      if (e != hipSuccess) return e;
+      pending = false;
+    }
+    if (!done) {
+      hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    if (bytes <= cap) return hipSuccess;
+    if (host) hipHostFree(host);
+    if (dev) hipFree(dev);
+    host = nullptr;
+    dev = nullptr;
+    cap = 0;
+    size_t c = std::max<size_t>(bytes, 1 << 16);
+    hipError_t e = hipHostMalloc((void**)&host, c, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    e = hipMalloc((void**)&dev, c);
+    if (e != hipSuccess) return e;
+    cap = c;
+    return hipSuccess;
+  }
+};
+
+static int batch_kind(const spider_plan_s* p) {
+  if (p->ndim == 2) return p->r == 1 ? kB2dR1 : (p->r == 2 ? kB2dR2 : kB2dR3);
+  // 3-D r = 1: star variant when every non-zero kernel row lies on the axes cross
+  const uint32_t star = (1u << 1) | (1u << 3) | (1u << 4) | (1u << 5) | (1u << 7);
+  return (p->rowmask & ~star) == 0 ? kB3dStar : kB3dBox;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Enqueue the batched time loop of `items` on stream s.
+spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, hipStream_t s, int nwg_cap) {
+  const int n = (int)items.size();
+  int operand = -1, engine = -1, maxsteps = 0;
+  for (const auto& it : items) {
+    const spider_plan_s* p = it.plan;
+    if (p->engine == SPIDER_ENGINE_DIRECT)
+      return fail(SPIDER_ERR_UNSUPPORTED, "batched apply runs the matrix engines only (16-bit carries)");
+    if (p->ndim == 2 ? p->r > 3 : p->r != 1)
+      return fail(SPIDER_ERR_UNSUPPORTED, "batched apply supports 2-D radius 1..3 and 3-D radius 1");
+    if (operand < 0) {
+      operand = p->operand;
+      engine = p->engine;
+    } else if (operand != p->operand || engine != p->engine) {
+      return fail(SPIDER_ERR_UNSUPPORTED, "batched plans must share carry dtype and engine");
+    }
+    if (it.steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
+    maxsteps = std::max(maxsteps, it.steps);
+  }
+  // Per item: the first source, after the in == out copy when needed.
+  std::vector<const void*> src(n);
+  for (int i = 0; i < n; ++i) {
+    const BatchItem& it = items[i];
+    src[i] = it.in;
+    const size_t bytes = it.plan->grid_bytes;
+    if (it.steps == 0) {
+      if (it.in != it.out) {
+        hipError_t e = hipMemcpyAsync(it.out, it.in, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+      }
+    } else if (it.in == it.out && (it.steps - 1) % 2 == 0) {
+      hipError_t e = hipMemcpyAsync(it.scratch, it.in, bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+      src[i] = it.scratch;
+    }
+  }
+  if (maxsteps == 0) return SPIDER_OK;
+  // Descriptor layout per step: BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned,
+  // then one counter per step.
+  std::vector<size_t> off(maxsteps + 1);
+  std::vector<int> m(maxsteps);
+  size_t bytes = 0;
+  for (int st = 0; st < maxsteps; ++st) {
+    int cnt = 0;
+    for (const auto& it : items) cnt += it.steps > st;
+    m[st] = cnt;
+    off[st] = bytes;
+    bytes += align_up(cnt * sizeof(BandGrid) + cnt * sizeof(int) + (cnt + 1) * sizeof(int), 256);
+  }
+  off[maxsteps] = bytes;
+  const size_t counters_off = bytes;
+  bytes += align_up(maxsteps * sizeof(int), 256);
+
+  std::lock_guard<std::mutex> lk(A.mu);
+  hipError_t e = A.reserve(bytes);
+  if (e != hipSuccess) return hip_fail(e, "batch descriptor buffers");
+  std::vector<const void*> cur = src;
+  std::vector<int> units(maxsteps, 0);
+  for (int st = 0; st < maxsteps; ++st) {
+    char* base = A.host + off[st];
+    BandGrid* gd = reinterpret_cast<BandGrid*>(base);
+    int* kinds = reinterpret_cast<int*>(base + m[st] * sizeof(BandGrid));
+    int* begin = kinds + m[st];
+    int j = 0, acc = 0;
+    for (int i = 0; i < n; ++i) {
+      const BatchItem& it = items[i];
+      if (it.steps <= st) continue;
+      const int k = st + 1;
+      void* dst = ((it.steps - k) % 2 == 0) ? it.out : it.scratch;
+      BandGrid g = it.plan->grid_template;
+      g.in = cur[i];
+      g.out = dst;
+      cur[i] = dst;
+      gd[j] = g;
+      kinds[j] = batch_kind(it.plan);
+      begin[j] = acc;
+      acc += g.nblocks;
+      ++j;
+    }
+    begin[j] = acc;
+    units[st] = acc;
+  }
+  e = hipMemcpyAsync(A.dev, A.host, counters_off, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  int* counters = reinterpret_cast<int*>(A.dev + counters_off);
+  e = launch_zero_ints(counters, maxsteps, s);
+  if (e != hipSuccess) return hip_fail(e, "counter reset");
+  for (int st = 0; st < maxsteps; ++st) {
+    char* base = A.dev + off[st];
+    const BandGrid* gd = reinterpret_cast<const BandGrid*>(base);
+    const int* kinds = reinterpret_cast<const int*>(base + m[st] * sizeof(BandGrid));
+    const int* begin = kinds + m[st];
+    const int nwg = std::max(1, std::min(units[st], nwg_cap));
+    e = launch_band_batch(operand, engine, gd, kinds, begin, m[st], counters + st, nwg, s);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  }
+  e = hipEventRecord(A.done, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  A.pending = true;
+  return SPIDER_OK;
+}
+
+static int batch_nwg_cap(int operand, int engine) {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  int per = band_batch_blocks_per_cu(operand, engine);
+  return ncu * std::max(per, 1);
+}
+
+static BatchArena& global_arena() {
+  static BatchArena* a = new BatchArena();  // lives until process exit
+  return *a;
+}
+
+}  // namespace spider_impl
+
+// =========================================================================== server
+
+struct ServerRequest {
+  uint64_t ticket = 0;
+  spider_plan_s* plan = nullptr;
+  const void* in = nullptr;
+  void* out = nullptr;
+  int steps = 0;
+  int remaining = 0;
+  bool started = false;
+  void* scratch = nullptr;
+  size_t footprint = 0;
+  std::chrono::steady_clock::time_point t_submit;
+  bool done = false;
+  spider_status result = SPIDER_OK;
+};
+
+struct spider_server_s {
+  size_t budget = 0, used = 0;
+  int max_slots = 0, max_queue = 0;
+  int round_steps = 8;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<ServerRequest*> queue;
+  std::vector<ServerRequest*> active;
+  std::unordered_map<uint64_t, ServerRequest*> tickets;
+  uint64_t next_ticket = 1;
+  std::thread th;
+  bool stop = false;
+  hipStream_t stream = nullptr;
+  spider_impl::BatchArena arena;
+  std::map<size_t, std::vector<void*>> pool;  // idle scratch buffers by size
+  size_t pooled = 0;
+  std::vector<double> lat_us;
+  double updates = 0.0;
+};
+
+namespace {
+
+void* take_scratch(spider_server_s* S, size_t bytes) {
+  auto it = S->pool.find(bytes);
+  if (it != S->pool.end() && !it->second.empty()) {
+    void* p = it->second.back();
+    it->second.pop_back();
+    S->pooled -= bytes;
+    return p;
+  }
+  // free idle buffers of other sizes while the new buffer would exceed the budget
+  while (S->used + S->pooled + 2 * bytes > S->budget && S->pooled > 0) {
+    for (auto& kv : S->pool) {
+      if (!kv.second.empty()) {
+        hipFree(kv.second.back());
+        kv.second.pop_back();
+        S->pooled -= kv.first;
+        break;
+      }
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void give_scratch(spider_server_s* S, void* p, size_t bytes) {
+  if (!p) return;
+  S->pool[bytes].push_back(p);
+  S->pooled += bytes;
+}
+
+void finish(spider_server_s* S, ServerRequest* r, spider_status st) {
+  r->done = true;
+  r->result = st;
+  const double us =
+      std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - r->t_submit).count();
+  if (st == SPIDER_OK) {
+    S->lat_us.push_back(us);
+    double pts = (double)r->plan->nz * r->plan->ny * r->plan->nx;
+    S->updates += pts * r->steps;
+  }
+  give_scratch(S, r->scratch, r->plan->grid_bytes);
+  r->scratch = nullptr;
+  S->used -= r->footprint;
+}
+
+void server_loop(spider_server_s* S) {
+  hipSetDevice(S->device);
+  std::map<int, int> caps;  // resident workgroups of the batch kernel per (operand, engine)
+  for (;;) {
+    std::vector<ServerRequest*> round;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop && S->active.empty()) break;
+      // admission: FIFO while a slot is free and the footprint fits the budget
+      while (!S->stop && !S->queue.empty() && (int)S->active.size() < S->max_slots) {
+        ServerRequest* r = S->queue.front();
+        if (S->used + r->footprint > S->budget) break;
+        void* scr = take_scratch(S, r->plan->grid_bytes);
+        if (!scr) break;
+        S->queue.pop_front();
+        r->scratch = scr;
+        S->used += r->footprint;
+        S->active.push_back(r);
+      }
+      round = S->active;
+    }
+    if (round.empty()) {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv.wait_for(lk, std::chrono::milliseconds(1));
+      continue;
+    }
+    // one round: every admitted request advances by up to round_steps steps, one
+    // batched time loop per (operand dtype, engine) group
+    std::vector<int> adv;
+    std::map<int, std::vector<spider_impl::BatchItem>> groups;
+    for (ServerRequest* r : round) {
+      const int k = std::min(r->remaining, S->round_steps);
+      const int key = r->plan->operand * 8 + r->plan->engine;
+      groups[key].push_back({r->plan, r->started ? r->out : r->in, r->out, r->scratch, k});
+      adv.push_back(k);
+    }
+    spider_status st = SPIDER_OK;
+    for (auto& kv : groups) {
+      auto c = caps.find(kv.first);
+      if (c == caps.end())
+        c = caps.emplace(kv.first, spider_impl::batch_nwg_cap(kv.first / 8, kv.first % 8)).first;
+      st = spider_impl::enqueue_batch(S->arena, kv.second, S->stream, c->second);
+      if (st != SPIDER_OK) break;
+    }
+    if (st == SPIDER_OK && hipStreamSynchronize(S->stream) != hipSuccess) st = SPIDER_ERR_HIP;
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::vector<ServerRequest*> still;
+    for (size_t i = 0; i < round.size(); ++i) {
+      ServerRequest* r = round[i];
+      if (st != SPIDER_OK) {
+        finish(S, r, st);
+        continue;
+      }
+      r->started = true;
+      r->remaining -= adv[i];
+      if (r->remaining <= 0)
+        finish(S, r, SPIDER_OK);
+      else
+        still.push_back(r);
+    }
+    S->active.swap(still);
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -12,26 +371,116 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
                                  const int* steps, void* stream) {
   clear_err();
   if (n < 1 || n > 4096 || !plans || !ins || !outs || !steps) return fail(SPIDER_ERR_INVALID, "bad batch arguments");
+  std::vector<BatchItem> items;
   for (int i = 0; i < n; ++i) {
-    spider_status st = spider_apply(plans[i], ins[i], outs[i], steps[i], stream);
-    if (st != SPIDER_OK) return st;
+    if (!plans[i] || !ins[i] || !outs[i]) return fail(SPIDER_ERR_INVALID, "NULL plan or grid in batch entry %d", i);
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i])
+        return fail(SPIDER_ERR_INVALID, "a plan appears twice in one batch (its scratch buffer is per plan)");
+    items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
+  const int cap = batch_nwg_cap(plans[0]->operand, plans[0]->engine);
+  return enqueue_batch(global_arena(), items, static_cast<hipStream_t>(stream), cap);
+}
+
+spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue, spider_server_t* out) {
+  clear_err();
+  if (!out) return fail(SPIDER_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (hbm_budget_bytes == 0 || max_slots < 1 || max_slots > 4096 || max_queue < 1)
+    return fail(SPIDER_ERR_INVALID, "budget must be > 0, max_slots in 1..4096, max_queue >= 1");
+  auto* S = new spider_server_s();
+  S->budget = hbm_budget_bytes;
+  S->max_slots = max_slots;
+  S->max_queue = max_queue;
+  hipError_t e = hipGetDevice(&S->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete S;
+    return hip_fail(e, "server stream");
+  }
+  S->th = std::thread(server_loop, S);
+  *out = S;
   return SPIDER_OK;
 }
 
-spider_status spider_server_create(size_t, int, int, spider_server_t* out) {
-  if (out) *out = nullptr;
-  return fail(SPIDER_ERR_UNSUPPORTED, "server not built yet");
+spider_status spider_submit(spider_server_t S, spider_plan_t plan, const void* in, void* out, int steps,
+                            uint64_t* ticket) {
+  clear_err();
+  if (!S || !plan || !in || !out || !ticket || steps < 0) return fail(SPIDER_ERR_INVALID, "bad submit arguments");
+  if (plan->engine == SPIDER_ENGINE_DIRECT || (plan->ndim == 2 ? plan->r > 3 : plan->r != 1))
+    return fail(SPIDER_ERR_UNSUPPORTED, "the server runs 16-bit plans: 2-D radius 1..3, 3-D radius 1");
+  const size_t fp = 2 * plan->grid_bytes;
+  if (fp > S->budget) return fail(SPIDER_ERR_OOM, "request needs %zu bytes, budget is %zu", fp, S->budget);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) return fail(SPIDER_ERR_CLOSED, "server is shutting down");
+  if ((int)S->queue.size() >= S->max_queue) return fail(SPIDER_ERR_BUSY, "queue full");
+  auto* r = new ServerRequest();
+  r->ticket = S->next_ticket++;
+  r->plan = plan;
+  r->in = in;
+  r->out = out;
+  r->steps = steps;
+  r->remaining = steps;
+  r->footprint = fp;
+  r->t_submit = std::chrono::steady_clock::now();
+  S->tickets[r->ticket] = r;
+  S->queue.push_back(r);
+  *ticket = r->ticket;
+  S->cv.notify_all();
+  return SPIDER_OK;
 }
-spider_status spider_submit(spider_server_t, spider_plan_t, const void*, void*, int, uint64_t*) {
-  return fail(SPIDER_ERR_UNSUPPORTED, "server not built yet");
+
+spider_status spider_poll(spider_server_t S, uint64_t ticket, int* done, spider_status* result) {
+  clear_err();
+  if (!S || !done) return fail(SPIDER_ERR_INVALID, "bad poll arguments");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return fail(SPIDER_ERR_CLOSED, "unknown ticket %llu", (unsigned long long)ticket);
+  *done = it->second->done ? 1 : 0;
+  if (result) *result = it->second->done ? it->second->result : SPIDER_ERR_NOT_READY;
+  return SPIDER_OK;
 }
-spider_status spider_poll(spider_server_t, uint64_t, int*, spider_status*) {
-  return fail(SPIDER_ERR_UNSUPPORTED, "server not built yet");
+
+spider_status spider_server_stats(spider_server_t S, double* p50_us, double* p99_us, uint64_t* completed,
+                                  double* stencil_updates) {
+  clear_err();
+  if (!S) return fail(SPIDER_ERR_INVALID, "server is NULL");
+  std::lock_guard<std::mutex> lk(S->mu);
+  std::vector<double> v = S->lat_us;
+  std::sort(v.begin(), v.end());
+  auto pct = [&](double q) {
+    if (v.empty()) return 0.0;
+    const size_t i = std::min(v.size() - 1, (size_t)(q * (v.size() - 1) + 0.5));
+    return v[i];
+  };
+  if (p50_us) *p50_us = pct(0.50);
+  if (p99_us) *p99_us = pct(0.99);
+  if (completed) *completed = v.size();
+  if (stencil_updates) *stencil_updates = S->updates;
+  return SPIDER_OK;
 }
-spider_status spider_server_stats(spider_server_t, double*, double*, uint64_t*, double*) {
-  return fail(SPIDER_ERR_UNSUPPORTED, "server not built yet");
+
+spider_status spider_server_destroy(spider_server_t S) {
+  if (!S) return SPIDER_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    // queued (not admitted) requests fail with CLOSED; admitted ones finish their steps
+    for (ServerRequest* r : S->queue) {
+      r->done = true;
+      r->result = SPIDER_ERR_CLOSED;
+    }
+    S->queue.clear();
+  }
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  for (auto& kv : S->pool)
+    for (void* p : kv.second) hipFree(p);
+  for (auto& kv : S->tickets) delete kv.second;
+  if (S->stream) hipStreamDestroy(S->stream);
+  delete S;
+  return SPIDER_OK;
 }
-spider_status spider_server_destroy(spider_server_t) { return SPIDER_OK; }
 
 }  // extern "C"

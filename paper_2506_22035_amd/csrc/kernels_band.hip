@@ -392,4 +392,89 @@ int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned) {
   return 0;
 }
 
+
+// ----------------------------------------------------------------------------- batched
+
+template <int OP, int ENG>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void band_batch_kernel(
+    const BandGrid* __restrict__ grids, const int* __restrict__ kinds, const int* __restrict__ begin, int n,
+    int* __restrict__ counter) {
+  constexpr int kLds = (7 * kLdsRowDw > 6 * kLdsRowDw ? 7 * kLdsRowDw : 6 * kLdsRowDw) + kLdsSpareDw;
+  __shared__ uint32_t lds[kLds];
+  const int total = begin[n];
+  for (;;) {
+    int unit = 0;
+    if (threadIdx.x == 0) unit = atomicAdd(counter, 1);
+    unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
+    if (unit >= total) break;  // every wave reaches this exit once the queue is drained
+    // grid owning `unit`: last i with begin[i] <= unit
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (begin[mid] <= unit) lo = mid;
+      else hi = mid - 1;
+    }
+    const BandGrid g = grids[lo];
+    const int w = unit - begin[lo];
+    const bool al = (g.nx % 8) == 0;
+    switch (kinds[lo]) {
+      case kB2dR1:
+        if (al) band2d_body<1, OP, ENG, true>(g, w, lds); else band2d_body<1, OP, ENG, false>(g, w, lds);
+        break;
+      case kB2dR2:
+        if (al) band2d_body<2, OP, ENG, true>(g, w, lds); else band2d_body<2, OP, ENG, false>(g, w, lds);
+        break;
+      case kB2dR3:
+        if (al) band2d_body<3, OP, ENG, true>(g, w, lds); else band2d_body<3, OP, ENG, false>(g, w, lds);
+        break;
+      case kB3dBox:
+        if (al) band3d_body<1, OP, ENG, true, box_mask3<1>()>(g, w, lds);
+        else band3d_body<1, OP, ENG, false, box_mask3<1>()>(g, w, lds);
+        break;
+      default:
+        if (al) band3d_body<1, OP, ENG, true, star_mask3<1>()>(g, w, lds);
+        else band3d_body<1, OP, ENG, false, star_mask3<1>()>(g, w, lds);
+        break;
+    }
+    wave_lds_sync();  // LDS reuse by the next unit
+  }
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_batch(int operand, int engine, const BandGrid* grids, const int* kinds, const int* begin, int n,
+                             int* counter, int nwg, hipStream_t s) {
+  const dim3 grid(nwg), block(64);
+  if (operand == 2 && engine == 1)
+    hipLaunchKernelGGL((band_batch_kernel<2, 1>), grid, block, 0, s, grids, kinds, begin, n, counter);
+  else if (operand == 2 && engine == 2)
+    hipLaunchKernelGGL((band_batch_kernel<2, 2>), grid, block, 0, s, grids, kinds, begin, n, counter);
+  else if (operand == 3 && engine == 1)
+    hipLaunchKernelGGL((band_batch_kernel<3, 1>), grid, block, 0, s, grids, kinds, begin, n, counter);
+  else if (operand == 3 && engine == 2)
+    hipLaunchKernelGGL((band_batch_kernel<3, 2>), grid, block, 0, s, grids, kinds, begin, n, counter);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int band_batch_blocks_per_cu(int operand, int engine) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (operand == 2 && engine == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<2, 1>, 64, 0);
+  if (operand == 2 && engine == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<2, 2>, 64, 0);
+  if (operand == 3 && engine == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<3, 1>, 64, 0);
+  if (operand == 3 && engine == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<3, 2>, 64, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
 }  // namespace spider_impl

@@ -308,6 +308,13 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     spider_plan_destroy(p);
     return fail(SPIDER_ERR_OOM, "scratch allocation of %zu bytes failed: %s", p->grid_bytes, hipGetErrorString(e));
   }
+  if (o.autotune && o.tile_h == 0) {
+    spider_status st = autotune_tile(p);
+    if (st != SPIDER_OK) {
+      spider_plan_destroy(p);
+      return st;
+    }
+  }
   *out = p;
   return SPIDER_OK;
 }

@@ -1,0 +1,176 @@
+"""Batched launches and the continuous-batching server on the GPU (through the C ABI).
+
+The batched kernel runs the same per-grid arithmetic as the single-grid
+kernels, so every batched or served result must equal the grid's result when it
+runs alone, bit for bit, and match the fp64 oracle within the mode's tolerance.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2506_22035_amd as sp
+import stencil_inputs as si
+from gpu_helpers import from_dev, rel_errors, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(carry="f16"):
+    """Four small grids of different shape and stencil."""
+    out = []
+    for name in ["box2d49p_10240", "star2d13p_8192", "box3d27p_512", "heat3d_256"]:
+        wl = si.workload(name, small=True)
+        xd, x64 = to_dev(wl["make_grid"](), carry)
+        out.append((wl, xd, x64))
+    out.append((dict(coeffs=si.coeffs_uniform01(2, 1, 1), shape=(200, 333), steps=7),) +
+               to_dev(si.grid_uniform01((200, 333), 9), carry))
+    return out
+
+
+def _alone(wl, xd, steps, carry="f16", engine="sparse"):
+    import torch
+    p = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, engine=engine)
+    y = torch.empty_like(xd)
+    p.apply(xd, y, steps)
+    return from_dev(y)
+
+
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+def test_batch_equals_alone(oracle_mod, engine):
+    import torch
+    mix = _mix()
+    plans = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", engine=engine) for wl, _, _ in mix]
+    outs = [torch.empty_like(xd) for _, xd, _ in mix]
+    steps = [wl["steps"] for wl, _, _ in mix]
+    steps[1] = 3  # uneven step counts
+    sp.apply_batch(plans, [xd for _, xd, _ in mix], outs, steps)
+    for (wl, xd, x64), o, st in zip(mix, outs, steps):
+        got = from_dev(o)
+        assert np.array_equal(got, _alone(wl, xd, st, engine=engine))
+        rms, mx = rel_errors(got, oracle_mod.apply(wl["coeffs"], x64, st))
+        assert rms <= 2e-3 and mx <= 1e-2
+
+
+def test_batch_integer_exact_aliasing_and_zero_steps(oracle_mod):
+    import torch
+    shapes = [(70, 300), (9, 10, 264), (33, 520)]
+    plans, xs, x64s, ws = [], [], [], []
+    for i, sh in enumerate(shapes):
+        w = si.integer_coeffs(len(sh), 1, -1, 1, 70 + i, "box")
+        xd, x64 = to_dev(si.grid_integer(sh, -1, 1, 80 + i), "f16")
+        plans.append(sp.Plan(w, sh, carry="f16"))
+        xs.append(xd)
+        x64s.append(x64)
+        ws.append(w)
+    steps = [2, 1, 0]
+    ins = [x.clone() for x in xs]
+    outs = [ins[0], torch.empty_like(xs[1]), torch.empty_like(xs[2])]  # grid 0 in place
+    sp.apply_batch(plans, ins, outs, steps)
+    for i in range(3):
+        assert np.array_equal(from_dev(outs[i]), oracle_mod.apply(ws[i], x64s[i], steps[i])), i
+
+
+def test_batch_rejects_bad_input():
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    p = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+    y = torch.empty_like(xd)
+    with pytest.raises(sp.SpiderError):
+        sp.apply_batch([p, p], [xd, xd], [y, y], [1, 1])  # one plan twice
+    p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32")
+    xf, _ = to_dev(wl["make_grid"](), "f32")
+    with pytest.raises(sp.SpiderError):
+        sp.apply_batch([p32], [xf], [torch.empty_like(xf)], [1])
+
+
+def _wait(srv, tickets, timeout=60.0):
+    t0 = time.time()
+    res = {}
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                done, st = srv.poll(t)
+                if done:
+                    res[t] = st
+        if time.time() - t0 > timeout:
+            raise TimeoutError("server did not finish")
+        time.sleep(0.001)
+    return res
+
+
+def test_server_results_equal_alone_in_the_mix():
+    import torch
+    mix = _mix()
+    srv = sp.Server(hbm_budget_bytes=1 << 30, max_slots=16)
+    plans, outs, tickets = [], [], []
+    try:
+        # several requests per plan, arriving while others are running
+        for rep in range(3):
+            for k, (wl, xd, _) in enumerate(mix):
+                p = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+                o = torch.empty_like(xd)
+                st = wl["steps"] + rep * 5
+                tickets.append((srv.submit(p, xd, o, st), k, st))
+                plans.append(p)
+                outs.append(o)
+            time.sleep(0.002)
+        res = _wait(srv, [t for t, _, _ in tickets])
+        assert all(v == 0 for v in res.values())
+        for (t, k, st), o in zip(tickets, outs):
+            wl, xd, _ = mix[k]
+            assert np.array_equal(from_dev(o), _alone(wl, xd, st)), (k, st)
+        stats = srv.stats()
+        assert stats["completed"] == len(tickets) and stats["p99_us"] >= stats["p50_us"] > 0
+    finally:
+        srv.close()
+
+
+def test_server_admission_by_footprint():
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    grid_bytes = xd.numel() * 2
+    # room for exactly one request (two grid-sized buffers) at a time
+    srv = sp.Server(hbm_budget_bytes=2 * grid_bytes + 100, max_slots=8, max_queue=3)
+    try:
+        plans = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16") for _ in range(3)]
+        outs = [torch.empty_like(xd) for _ in range(3)]
+        ts = [srv.submit(p, xd, o, 20) for p, o in zip(plans, outs)]
+        res = _wait(srv, ts)
+        assert all(v == 0 for v in res.values())
+        ref = _alone(wl, xd, 20)
+        for o in outs:
+            assert np.array_equal(from_dev(o), ref)
+        big = si.workload("box2d49p_10240", small=False)
+        pbig = sp.Plan(big["coeffs"], (1024, 1024), carry="f16")
+        xb = torch.zeros((1024, 1024), dtype=torch.float16, device="cuda")
+        with pytest.raises(sp.SpiderError) as e:
+            srv.submit(pbig, xb, xb, 1)
+        assert e.value.status == 3  # OOM: alone exceeds the budget
+        with pytest.raises(sp.SpiderError) as e:
+            srv.poll(987654321)
+        assert e.value.status == 7
+    finally:
+        srv.close()
+
+
+def test_server_queue_full_and_close():
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    srv = sp.Server(hbm_budget_bytes=2 * xd.numel() * 2 + 100, max_slots=1, max_queue=2)
+    plans = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16") for _ in range(6)]
+    outs = [torch.empty_like(xd) for _ in range(6)]
+    got_busy = False
+    ts = []
+    for p, o in zip(plans, outs):
+        t = srv.try_submit(p, xd, o, 200)
+        if t is None:
+            got_busy = True
+        else:
+            ts.append(t)
+    assert got_busy
+    srv.close()  # admitted requests finish, queued ones fail with CLOSED
+    torch.cuda.synchronize()
