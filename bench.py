@@ -79,6 +79,61 @@ def cone_samples(oracle, w, x64, steps, pts):
     return np.array(out)
 
 
+def serving_run(torch, sp, si, reqs, rate, plans, bases, budget, slots):
+    """Submit `reqs` (arrival times scaled to `rate` req/s) to a fresh server; return stats."""
+    srv = sp.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=len(reqs) + 1)
+    outs = {}
+    pending = []
+    t0 = time.perf_counter()
+    try:
+        for r in reqs:
+            t_arr = r["t"] / rate
+            while time.perf_counter() - t0 < t_arr:
+                # poll while waiting so finished outputs are released
+                for tk in list(outs):
+                    if srv.poll(tk)[0]:
+                        del outs[tk]
+            shape = tuple(r["shape"])
+            key = (r["stencil"], shape)
+            if key not in plans:
+                plans[key] = sp.Plan(si.serving_coeffs(r["stencil"]), shape, carry="f16")
+            n = int(np.prod(shape))
+            xin = bases[len(shape)][:n].view(shape)
+            o = torch.empty(shape, dtype=torch.float16, device="cuda")
+            tk = srv.submit(plans[key], xin, o, r["steps"])
+            outs[tk] = o
+            pending.append(tk)
+        for tk in pending:
+            while not srv.poll(tk)[0]:
+                time.sleep(0.0002)
+        t1 = time.perf_counter()
+        st = srv.stats()
+    finally:
+        srv.close()
+    return {"rate_req_s": round(rate, 2), "requests": len(reqs), "p50_ms": round(st["p50_us"] / 1e3, 3),
+            "p99_ms": round(st["p99_us"] / 1e3, 3), "GStencil/s": round(st["stencil_updates"] / (t1 - t0) / 1e9, 2),
+            "wall_s": round(t1 - t0, 3)}
+
+
+def serving(torch, sp, si, n, fractions, seed=11):
+    """Serving mix: saturation throughput first (all requests at once), then Poisson rates."""
+    torch.manual_seed(seed)
+    bases = {2: (torch.rand(8192 * 8192, device="cuda") ).to(torch.float16),
+             3: (torch.rand(384 ** 3, device="cuda")).to(torch.float16)}
+    plans = {}
+    reqs = si.serving_requests(n, 1.0, seed)   # times for rate 1 req/s, rescaled per run
+    budget, slots = 32 << 30, 64
+    sat = serving_run(torch, sp, si, [dict(r, t=0.0) for r in reqs], 1.0, plans, bases, budget, slots)
+    sat_rate = n / sat["wall_s"]
+    out = {"saturation": dict(sat, rate_req_s=round(sat_rate, 2)), "sweep": []}
+    for f in fractions:
+        out["sweep"].append(dict(serving_run(torch, sp, si, reqs, f * sat_rate, plans, bases, budget, slots),
+                                 load=f))
+    for p in plans.values():
+        p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +146,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip errors, fp32 path and ablation")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of the grid size (for HBM counter scaling)")
+    ap.add_argument("--serving", action="store_true",
+                    help="run only the serving-mix sweep (1000 requests per rate) and print its JSON line")
+    ap.add_argument("--serving-requests", type=int, default=1000)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -102,6 +160,14 @@ def main():
 
     import paper_2506_22035_amd as sp
     import stencil_inputs as si
+
+    if args.serving:
+        res = serving(torch, sp, si, args.serving_requests, [0.25, 0.5, 1.0, 1.5])
+        print(json.dumps({"metric": "serving mix: p50/p99 latency (ms) and GStencil/s per Poisson rate",
+                          "config": {"workload": "serving_mix", "stencils": list(si.SERVING_STENCILS),
+                                     "grids_2d": "512^2..8192^2", "grids_3d": "64^3..384^3", "steps": "1..100",
+                                     "carry": "f16"}, "serving": res}))
+        return
 
     wl = si.workload("box2d49p_10240")
     T = wl["steps"]
@@ -115,7 +181,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
-    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=args.carry, engine=args.engine, tile_h=args.tile_h)
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=args.carry, engine=args.engine, tile_h=args.tile_h,
+                   autotune=True)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
 
@@ -208,6 +275,10 @@ def main():
             abl["%s_%s" % (engine, carry)] = round(npts * T * 3 / (msa * 1e-3) / 1e9, 2)
             pa.close()
         out["ablation_gstencil_s"] = abl
+
+    if not args.no_extras:
+        # a short serving sample (the full sweep is `bench.py --serving`)
+        out["serving_sample"] = serving(torch, sp, si, 200, [0.75])
 
     if not args.no_cpu_baseline:
         import oracle

@@ -90,8 +90,9 @@ spider_status spider_opts_default(spider_opts* o);
  *   out     receives the plan handle
  * Builds, per kernel row with a non-zero tap, the banded matrix, pads it, applies
  * the strided column swap, splits coefficients into 16-bit hi/lo parts, compresses
- * to 2:4 values + 2-bit indices and packs them in the gfx950 lane order; uploads
- * them and allocates one grid-sized scratch buffer on the current HIP device.
+ * to 2:4 values + 2-bit indices and packs them in the gfx950 lane order and uploads
+ * them to the current HIP device.  A grid-sized scratch buffer is allocated on the
+ * first spider_apply / spider_apply_batch (or at plan time when autotuning).
  * Errors: INVALID (arguments), UNSUPPORTED (e.g. sparse engine with an fp32/fp64
  * carry), OOM, HIP.  The plan is immutable after creation and owns its device memory.
  */
@@ -115,7 +116,8 @@ spider_status spider_plan_destroy(spider_plan_t plan);
 /*
  * spider_plan_info: describe a plan (host query, no device work).
  *   engine, carry, tile_h, nrows_nonzero (kernel rows on the matrix path),
- *   scratch_bytes (device bytes the plan owns).  Any output pointer may be NULL.
+ *   scratch_bytes (size of the grid-sized scratch buffer the plan allocates on
+ *   first use).  Any output pointer may be NULL.
  */
 spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int* tile_h,
                                int* nrows_nonzero, size_t* scratch_bytes);

@@ -42,6 +42,7 @@ spider_status fail(spider_status st, const char* fmt, ...);
 spider_status hip_fail(hipError_t e, const char* what);
 void clear_err();
 size_t dtype_bytes(int dt);
+spider_status ensure_scratch(spider_plan_s* p);
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
 // Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).

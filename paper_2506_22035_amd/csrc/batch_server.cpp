@@ -377,6 +377,10 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i])
         return fail(SPIDER_ERR_INVALID, "a plan appears twice in one batch (its scratch buffer is per plan)");
+    if (steps[i] > 0) {
+      spider_status st = ensure_scratch(plans[i]);
+      if (st != SPIDER_OK) return st;
+    }
     items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
   const int cap = batch_nwg_cap(plans[0]->operand, plans[0]->engine);

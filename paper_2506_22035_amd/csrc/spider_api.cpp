@@ -96,6 +96,18 @@ static int auto_tile_h_direct(const spider_plan_s* p) {
   return std::min(p->ny, 64);
 }
 
+// The grid-sized scratch buffer is allocated on first use, so plans that only
+// feed the server (which owns per-request scratch) never hold one.
+spider_status ensure_scratch(spider_plan_s* p) {
+  if (p->d_scratch) return SPIDER_OK;
+  hipError_t e = hipMalloc(&p->d_scratch, p->grid_bytes);
+  if (e != hipSuccess) {
+    p->d_scratch = nullptr;
+    return fail(SPIDER_ERR_OOM, "scratch allocation of %zu bytes failed: %s", p->grid_bytes, hipGetErrorString(e));
+  }
+  return SPIDER_OK;
+}
+
 // One time step of the plan from `src` to `dst` on `s`.
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
   hipError_t e;
@@ -303,13 +315,9 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     }
     g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
   }
-  e = hipMalloc(&p->d_scratch, p->grid_bytes);
-  if (e != hipSuccess) {
-    spider_plan_destroy(p);
-    return fail(SPIDER_ERR_OOM, "scratch allocation of %zu bytes failed: %s", p->grid_bytes, hipGetErrorString(e));
-  }
   if (o.autotune && o.tile_h == 0) {
-    spider_status st = autotune_tile(p);
+    spider_status st = ensure_scratch(p);
+    if (st == SPIDER_OK) st = autotune_tile(p);
     if (st != SPIDER_OK) {
       spider_plan_destroy(p);
       return st;
@@ -326,6 +334,10 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
   if (steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(p->mu);
+  if (steps > 0) {
+    spider_status st = ensure_scratch(p);
+    if (st != SPIDER_OK) return st;
+  }
   if (!p->use_graph || steps < 2) return enqueue_steps(p, in, out, steps, s);
   // Replay a graph of the whole time loop, captured once per (in, out, steps).
   auto key = std::make_tuple(in, (const void*)out, steps);
