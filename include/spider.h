@@ -70,7 +70,10 @@ typedef struct {
     int autotune;  /* 1 = when tile_h is 0, time candidate segment heights on the device at
                       plan time and keep the fastest (results cached per shape, radius,
                       engine and dtype for the life of the process); 0 = occupancy heuristic */
-    int reserved[2];
+    int time_block; /* time steps fused per launch: 0 = automatic (two for 2-D grids of
+                       radius <= 3 on the matrix engines, else one), 1 = one step per launch,
+                       2 = two where supported.  Results are identical bit for bit. */
+    int reserved[1];
 } spider_opts;
 
 typedef struct spider_plan_s* spider_plan_t;
@@ -115,12 +118,15 @@ spider_status spider_plan_destroy(spider_plan_t plan);
 
 /*
  * spider_plan_info: describe a plan (host query, no device work).
- *   engine, carry, tile_h, nrows_nonzero (kernel rows on the matrix path),
- *   scratch_bytes (size of the grid-sized scratch buffer the plan allocates on
- *   first use).  Any output pointer may be NULL.
+ *   engine, carry, tile_h (segment height of the one-step kernel), nrows_nonzero
+ *   (kernel rows on the matrix path), scratch_bytes (size of the grid-sized scratch
+ *   buffer the plan allocates on first use), time_block (steps fused per launch),
+ *   tile_h2 (segment height of the two-step kernel, 0 if unused).  Any output
+ *   pointer may be NULL.
  */
 spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int* tile_h,
-                               int* nrows_nonzero, size_t* scratch_bytes);
+                               int* nrows_nonzero, size_t* scratch_bytes, int* time_block,
+                               int* tile_h2);
 
 /*
  * Batched apply (one launch per time step over the tiles of every grid).

@@ -33,7 +33,7 @@ class SpiderError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("carry", ctypes.c_int), ("engine", ctypes.c_int), ("split", ctypes.c_int),
                 ("tile_h", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("time_block", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 _lib = None
@@ -52,7 +52,7 @@ def lib():
             "spider_plan": [P, I, P, I, P, P],
             "spider_apply": [P, P, P, I, P],
             "spider_plan_destroy": [P],
-            "spider_plan_info": [P, P, P, P, P, P],
+            "spider_plan_info": [P, P, P, P, P, P, P, P],
             "spider_apply_batch": [I, P, P, P, P, P],
             "spider_server_create": [ctypes.c_size_t, I, I, P],
             "spider_submit": [P, P, P, P, I, P],
@@ -149,7 +149,8 @@ class Plan:
     """A stencil plan: coefficients (2r+1,)*ndim (w[dz][dy][dx] multiplies x[p + offset]),
     grid shape, carry dtype and engine.  Owns device memory until `close()`."""
 
-    def __init__(self, coeffs, shape, carry="f16", engine="auto", split=2, tile_h=0, use_graph=True, autotune=False):
+    def __init__(self, coeffs, shape, carry="f16", engine="auto", split=2, tile_h=0, use_graph=True, autotune=False,
+                 time_block=0):
         w = np.ascontiguousarray(coeffs, dtype=np.float64)
         ndim = len(shape)
         if w.ndim != ndim or len(set(w.shape)) != 1 or w.shape[0] % 2 != 1:
@@ -165,6 +166,7 @@ class Plan:
         opts.tile_h = int(tile_h)
         opts.use_graph = 1 if use_graph else 0
         opts.autotune = 1 if autotune else 0
+        opts.time_block = int(time_block)
         shp = (ctypes.c_int64 * ndim)(*self.shape)
         h = ctypes.c_void_p()
         _check(lib().spider_plan(_ptr(w), ndim, shp, self.radius, ctypes.byref(opts), ctypes.byref(h)))
@@ -177,12 +179,12 @@ class Plan:
         return self._h
 
     def info(self):
-        e, c, t, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        e, c, t, n, tb, t2 = (ctypes.c_int() for _ in range(6))
         sb = ctypes.c_size_t()
         _check(lib().spider_plan_info(self.handle, ctypes.byref(e), ctypes.byref(c), ctypes.byref(t),
-                                      ctypes.byref(n), ctypes.byref(sb)))
+                                      ctypes.byref(n), ctypes.byref(sb), ctypes.byref(tb), ctypes.byref(t2)))
         return dict(engine=_ENGINE_NAMES[e.value], carry=_DTYPE_NAMES[c.value], tile_h=t.value,
-                    nrows_nonzero=n.value, scratch_bytes=sb.value)
+                    nrows_nonzero=n.value, scratch_bytes=sb.value, time_block=tb.value, tile_h2=t2.value)
 
     def check_tensor(self, t):
         torch = _torch()

@@ -32,6 +32,9 @@ struct spider_plan_s {
   void* d_scratch = nullptr;
   size_t grid_bytes = 0;
   spider_impl::BandGrid grid_template{};
+  int time_block = 1;                   // steps fused per launch of the matrix engines (1 or 2)
+  int tile_h2 = 0;                      // segment height of the two-step kernel
+  spider_impl::BandGrid grid_tb2{};     // two-step kernel: 240-wide strips
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
   std::mutex mu;
@@ -44,6 +47,9 @@ void clear_err();
 size_t dtype_bytes(int dt);
 spider_status ensure_scratch(spider_plan_s* p);
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
+// One launch of the two-step kernel (requires time_block == 2).
+spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
+void set_tile2(spider_plan_s* p, int h);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
 // Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).
 spider_status autotune_tile(spider_plan_s* p);

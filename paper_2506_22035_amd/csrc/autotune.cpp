@@ -24,6 +24,7 @@ namespace {
 using Key = std::tuple<int, int, int, int, int, int, int, uint32_t, bool>;
 std::mutex g_mu;
 std::map<Key, int> g_cache;
+std::map<Key, int> g_cache2;  // two-step kernel
 
 Key key_of(const spider_plan_s* p) {
   return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine, p->rowmask, p->has_zero_tap);
@@ -61,6 +62,8 @@ spider_status autotune_tile(spider_plan_s* p) {
     auto it = g_cache.find(k);
     if (it != g_cache.end()) {
       set_tile(p, it->second);
+      auto it2 = g_cache2.find(k);
+      if (p->time_block == 2 && it2 != g_cache2.end()) set_tile2(p, it2->second);
       return SPIDER_OK;
     }
   }
@@ -95,15 +98,39 @@ spider_status autotune_tile(spider_plan_s* p) {
       best = cand[i];
     }
   }
+  set_tile(p, best);
+  // the two-step kernel has its own height
+  int best2 = p->tile_h2;
+  if (e == hipSuccess && p->time_block == 2) {
+    float best2_ms = 1e30f;
+    const std::vector<int> cand2 = candidates(p->tile_h2, p->ny);
+    for (size_t i = 0; e == hipSuccess && i < cand2.size(); ++i) {
+      set_tile2(p, cand2[i]);
+      if (launch_step2(p, p->d_scratch, tmp, s) != SPIDER_OK) break;
+      e = hipEventRecord(e0, s);
+      for (int r = 0; e == hipSuccess && r < reps; ++r)
+        if (launch_step2(p, (r & 1) ? tmp : p->d_scratch, (r & 1) ? p->d_scratch : tmp, s) != SPIDER_OK)
+          e = hipErrorUnknown;
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess && ms < best2_ms) {
+        best2_ms = ms;
+        best2 = cand2[i];
+      }
+    }
+    set_tile2(p, best2);
+  }
   if (s) hipStreamSynchronize(s);
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
   if (s) hipStreamDestroy(s);
   hipFree(tmp);
-  set_tile(p, best);
   if (e != hipSuccess) return hip_fail(e, "autotune");
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[k] = best;
+  g_cache2[k] = best2;
   return SPIDER_OK;
 }
 

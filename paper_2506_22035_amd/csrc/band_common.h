@@ -125,12 +125,16 @@ __device__ __forceinline__ uint32_t out_voffset(int x0, int lane) {
   return (uint32_t)((x0 + 16 * (lane & 15) + 4 * (lane >> 4)) * 2);
 }
 
+// Cache policy of output stores: non-temporal, so written lines do not displace
+// the input lines that neighbouring waves are about to re-read as halo.
+constexpr int kStoreNT = 2;
+
 // Store 4 packed 16-bit outputs; the line resource drops whatever lies outside [0, nx).
 template <bool ALIGNED>
 __device__ __forceinline__ void store_packed(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint2 w) {
   if constexpr (ALIGNED) {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64((u32x2){w.x, w.y}, rs, voff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64((u32x2){w.x, w.y}, rs, voff, 0, kStoreNT);
   } else {
     __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w.x & 0xffff), rs, voff, 0, 0);
     __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(w.x >> 16), rs, voff + 2, 0, 0);

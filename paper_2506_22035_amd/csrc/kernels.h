@@ -35,6 +35,12 @@ hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* grids_d
 hipError_t launch_band3d(int r, int operand, int engine, const BandGrid* grids_dev, const BandGrid* grids_host,
                          int n, hipStream_t s);
 
+// Two fused time steps per launch (2-D, r <= 3).  The grid's strips are
+// kStripW2_host = 240 outputs wide (nstrips = ceil(nx / 240)).
+constexpr int kStripW2_host = 240;
+hipError_t launch_band2d_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
+int band2d_tb2_blocks_per_cu(int r, int operand, int engine);
+
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
 int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);
@@ -66,7 +72,8 @@ constexpr int kRowsY3 = 4;
 hipError_t launch_direct(int ndim, int r, int dtype, bool skip_zero_taps, const void* in, void* out, int nz, int ny,
                          int nx, const void* coeffs_dev, int seg_h, hipStream_t s);
 
-// Rows of the 2-D band wave: stride between wave strips along x.
+// Outputs per 2-D band wave strip; strip s covers x in [256 s - 8, 256 s + 248),
+// so a 2-D grid has ceil((nx + 8) / 256) strips.
 constexpr int kStripW = 256;
 
 }  // namespace spider_impl

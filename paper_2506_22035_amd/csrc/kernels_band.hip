@@ -27,17 +27,27 @@ namespace spider_impl {
 
 // ----------------------------------------------------------------------------- 2-D
 
+// Every output line accumulates its kernel rows in the same order (0 .. 2R),
+// whatever the segmentation, so results do not depend on the tile height, on
+// batching or on how many steps a launch fuses.
 template <int R, int OP, int ENG, bool ALIGNED>
 __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int RR = 2 * R + 1;
   constexpr int U = (RR >= 5) ? RR : 2 * RR;  // unroll = prefetch depth, multiple of RR
   const int lane = threadIdx.x;
   const int strip = w % g.nstrips, seg = w / g.nstrips;
-  const int x0 = strip * kStripW;
+  // Chunks start at x = 8 (mod 16) in every 2-D kernel, so a point always sits at
+  // the same row of its 16-point chunk and is summed in the same order (the
+  // first strip's 8 outputs left of x = 0 fall outside the line and are dropped).
+  const int x0 = strip * kStripW - 8;
   const int y0 = seg * g.seg_h;
   const int hrows = min(g.seg_h, g.ny - y0);        // output rows of this segment
   const int nin = ((hrows + 2 * R + U - 1) / U) * U;  // input rows streamed, padded to U
   const int nx = g.nx, ny = g.ny;
+
+  // input line j and output line i of the stream, in grid rows
+  auto in_row = [&](int j) { return y0 - R + j; };
+  auto out_row = [&](int i) { return y0 + i; };
 
   // Register-resident kernel operands (Sec. 3.3.1: the kernel matrix bypasses shared memory).
   u32x4 A[RR], Dh[RR], Dl[RR];
@@ -73,7 +83,7 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
   u32x4 stg[U];
 #pragma unroll
   for (int q = 0; q < U; ++q) {
-    const int y = y0 - R + q;
+    const int y = in_row(q);
     const bool valid = q < hrows + 2 * R && y >= 0 && y < ny;
     stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
   }
@@ -94,13 +104,13 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
       for (int q = 0; q < U; ++q) {
         const int i = jb - U + q - 2 * R;
         const bool ovalid = i >= 0 && i < hrows;
-        store_packed<ALIGNED>(line_rsrc(g.out, (size_t)(y0 + i) * nx, nx, ovalid, 2), ovoff, done[q]);
+        store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i) * nx, nx, ovalid, 2), ovoff, done[q]);
       }
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int jn = jb + U + q;
-      const int y = y0 - R + jn;
+      const int y = in_row(jn);
       const bool valid = jn < hrows + 2 * R && y >= 0 && y < ny;
       stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
     }
@@ -129,9 +139,11 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
   for (int q = 0; q < U; ++q) {
     const int i = nin - U + q - 2 * R;
     const bool ovalid = i >= 0 && i < hrows;
-    store_packed<ALIGNED>(line_rsrc(g.out, (size_t)(y0 + i) * nx, nx, ovalid, 2), ovoff, done[q]);
+    store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i) * nx, nx, ovalid, 2), ovoff, done[q]);
   }
 }
+
+
 
 template <int R, int OP, int ENG, bool ALIGNED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && ENG == 1) ? 4 : (R <= 3 ? 3 : 2))))
@@ -141,6 +153,166 @@ void band2d_kernel(BandGrid g) {
   __shared__ uint32_t lds[U * kLdsRowDw + kLdsSpareDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   band2d_body<R, OP, ENG, ALIGNED>(g, w, lds);
+}
+
+// ----------------------------------------------------------------------------- 2-D, two fused steps
+// Temporal blocking (two time steps per launch).  The wave's first pass is the
+// single-step pass on 16 chunks starting 8 columns left of the stored strip
+// (x0 - 8 .. x0 + 248); each finished line of step s+1 is rounded to the carry
+// type exactly as a stored step would be, zeroed outside the grid (the zero
+// halo of step s+1), written to an LDS line in the same padded layout, and
+// multiplied again (second pass) into a second set of rotating accumulators.
+// Second-pass outputs are valid for x in [x0 - 8 + r, x0 + 248 - r); the wave
+// stores [x0, x0 + kStripW2).  Strips therefore advance by kStripW2 = 240.
+// The result equals two single-step launches bit for bit.
+constexpr int kStripW2 = 240;
+
+template <int OP>
+__device__ __forceinline__ uint2 pack_masked(f32x4 a, bool row_ok, int x, int nx) {
+  uint2 w = pack_out<OP>(a);
+  // lane's 4 values are x .. x+3; zero those outside the grid
+  uint32_t m0 = 0, m1 = 0;
+  if (row_ok) {
+    m0 = (x >= 0 && x < nx ? 0x0000ffffu : 0u) | (x + 1 >= 0 && x + 1 < nx ? 0xffff0000u : 0u);
+    m1 = (x + 2 >= 0 && x + 2 < nx ? 0x0000ffffu : 0u) | (x + 3 >= 0 && x + 3 < nx ? 0xffff0000u : 0u);
+  }
+  return make_uint2(w.x & m0, w.y & m1);
+}
+
+template <int R, int OP, int ENG, bool ALIGNED>
+__device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int U = (RR >= 5) ? RR : 2 * RR;
+  const int lane = threadIdx.x;
+  const int strip = w % g.nstrips, seg = w / g.nstrips;
+  const int x0 = strip * kStripW2;
+  const int y0 = seg * g.seg_h;
+  const int hrows = min(g.seg_h, g.ny - y0);
+  const int nin = ((hrows + 4 * R + U - 1) / U) * U;  // input lines streamed, padded to U
+  const int nx = g.nx, ny = g.ny;
+  auto in_row = [&](int j) { return y0 - 2 * R + j; };
+  auto mid_row = [&](int i1) { return y0 - R + i1; };
+  auto out_row = [&](int i2) { return y0 + i2; };
+
+  u32x4 A[RR], Dh[RR], Dl[RR];
+  uint32_t I[(RR + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < RR; ++a) {
+    if constexpr (ENG == 1) {
+      A[a] = reinterpret_cast<const u32x4*>(g.apack)[a * 64 + lane];
+      Dh[a] = Dl[a] = (u32x4){0, 0, 0, 0};
+    } else {
+      A[a] = (u32x4){0, 0, 0, 0};
+      Dh[a] = reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 0];
+      Dl[a] = reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 1];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < (RR + 1) / 2; ++a) I[a] = (ENG == 1) ? g.ipack[a * 64 + lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const uint32_t lvoff = chunk_voffset(x0 - 8, lane);       // staged line covers [x0 - 16, x0 + 256)
+  const int xl = x0 - 8 + 16 * (lane & 15) + 4 * (lane >> 4);  // this lane's 4 outputs of either pass
+  const uint32_t ovoff = (xl >= x0 && xl < x0 + kStripW2) ? (uint32_t)(xl * 2) : 0x7ffffff0u;
+  const int lw = chunk_lds_offset(lane, U * kLdsRowDw + 2 * kLdsRowDw);
+  const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
+  // second-pass LDS lines (two, alternating): this lane's 4 values sit at dword unit 4 + 8n + 2h
+  uint32_t* mid = lds + U * kLdsRowDw;
+  const int mw = lds_phys(4 + 8 * (lane & 15) + 2 * (lane >> 4));
+  // the 8 columns left of x0 - 8 and right of x0 + 248 are never computed: keep them zero
+  if (lane < 8) {
+    const int u = (lane & 3) + (lane < 4 ? 0 : 132);
+    mid[lds_phys(u)] = 0u;
+    mid[kLdsRowDw + lds_phys(u)] = 0u;
+  }
+
+  u32x4 stg[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int y = in_row(q);
+    const bool valid = q < hrows + 4 * R && y >= 0 && y < ny;
+    stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
+  }
+  f32x4 acc1[RR], acc2[RR];
+#pragma unroll
+  for (int s = 0; s < RR; ++s) acc1[s] = acc2[s] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  uint2 done[U];
+
+  for (int jb = 0; jb < nin; jb += U) {
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    if (jb > 0) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int i2 = jb - U + q - 4 * R;
+        const bool ovalid = i2 >= 0 && i2 < hrows;
+        store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i2) * nx, nx, ovalid, 2), ovoff, done[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int jn = jb + U + q;
+      const int y = in_row(jn);
+      const bool valid = jn < hrows + 4 * R && y >= 0 && y < ny;
+      stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = jb + q;
+      const uint32_t* lrow = lds + q * kLdsRowDw;
+      const u32x4 b = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+#pragma unroll
+      for (int a = 0; a < RR; ++a) {
+        const int slot = ((q - a) % RR + RR) % RR;
+        if (a & 1)
+          acc1[slot] = band_mma<OP, ENG, 1>(acc1[slot], A[a], Dh[a], Dl[a], I[a / 2], b);
+        else
+          acc1[slot] = band_mma<OP, ENG, 0>(acc1[slot], A[a], Dh[a], Dl[a], I[a / 2], b);
+      }
+      // first-pass line i1 = j - 2R is complete: it is step s+1 at mid_row(i1)
+      const int fs1 = (q + 1) % RR;
+      const int i1 = j - 2 * R;
+      const int ym = mid_row(i1);
+      const uint2 mv = pack_masked<OP>(acc1[fs1], i1 >= 0 && ym >= 0 && ym < ny, xl, nx);
+      acc1[fs1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      uint32_t* mrow = mid + (j & 1) * kLdsRowDw;
+      *reinterpret_cast<uint2*>(mrow + mw) = mv;
+      wave_lds_sync();
+      const u32x4 b2 = {mrow[p1], mrow[p1 + 10], mrow[p2], mrow[p2 + 10]};
+      // mid line i1 feeds second-pass output i2 = i1 - a: slot (q - 2R - a) mod RR
+#pragma unroll
+      for (int a = 0; a < RR; ++a) {
+        const int slot = ((q + 1 - a) % RR + RR) % RR;
+        if (a & 1)
+          acc2[slot] = band_mma<OP, ENG, 1>(acc2[slot], A[a], Dh[a], Dl[a], I[a / 2], b2);
+        else
+          acc2[slot] = band_mma<OP, ENG, 0>(acc2[slot], A[a], Dh[a], Dl[a], I[a / 2], b2);
+      }
+      // second-pass output i2 = j - 4R is complete
+      const int fs2 = (q + 2) % RR;
+      done[q] = pack_out<OP>(acc2[fs2]);
+      acc2[fs2] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int i2 = nin - U + q - 4 * R;
+    const bool ovalid = i2 >= 0 && i2 < hrows;
+    store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i2) * nx, nx, ovalid, 2), ovoff, done[q]);
+  }
+}
+
+template <int R, int OP, int ENG, bool ALIGNED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void band2d_tb2_kernel(BandGrid g) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int U = (RR >= 5) ? RR : 2 * RR;
+  __shared__ uint32_t lds[U * kLdsRowDw + 2 * kLdsRowDw + kLdsSpareDw];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band2d_tb2_body<R, OP, ENG, ALIGNED>(g, w, lds);
 }
 
 // ----------------------------------------------------------------------------- dispatch
@@ -159,6 +331,41 @@ static hipError_t dispatch2d(int r, const BandGrid& g, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int OP, int ENG, bool AL>
+static hipError_t dispatch2d_tb2(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  switch (r) {
+    case 1: hipLaunchKernelGGL((band2d_tb2_kernel<1, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band2d_tb2_kernel<2, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band2d_tb2_kernel<3, OP, ENG, AL>), grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_band2d_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2 && engine == 1) return al ? dispatch2d_tb2<2, 1, true>(r, g, s) : dispatch2d_tb2<2, 1, false>(r, g, s);
+  if (operand == 2 && engine == 2) return al ? dispatch2d_tb2<2, 2, true>(r, g, s) : dispatch2d_tb2<2, 2, false>(r, g, s);
+  if (operand == 3 && engine == 1) return al ? dispatch2d_tb2<3, 1, true>(r, g, s) : dispatch2d_tb2<3, 1, false>(r, g, s);
+  if (operand == 3 && engine == 2) return al ? dispatch2d_tb2<3, 2, true>(r, g, s) : dispatch2d_tb2<3, 2, false>(r, g, s);
+  return hipErrorInvalidValue;
+}
+
+int band2d_tb2_blocks_per_cu(int r, int operand, int engine) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define SPIDER_OCC_TB2(RV, OPV, ENGV)                                                                      \
+  if (r == RV && operand == OPV && engine == ENGV)                                                         \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_tb2_kernel<RV, OPV, ENGV, true>, 64, 0);
+  SPIDER_OCC_TB2(1, 2, 1) SPIDER_OCC_TB2(2, 2, 1) SPIDER_OCC_TB2(3, 2, 1)
+  SPIDER_OCC_TB2(1, 2, 2) SPIDER_OCC_TB2(2, 2, 2) SPIDER_OCC_TB2(3, 2, 2)
+  SPIDER_OCC_TB2(1, 3, 1) SPIDER_OCC_TB2(2, 3, 1) SPIDER_OCC_TB2(3, 3, 1)
+  SPIDER_OCC_TB2(1, 3, 2) SPIDER_OCC_TB2(2, 3, 2) SPIDER_OCC_TB2(3, 3, 2)
+#undef SPIDER_OCC_TB2
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* /*grids_dev*/, const BandGrid* grids_host,

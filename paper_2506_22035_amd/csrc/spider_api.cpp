@@ -63,7 +63,7 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
   int per_cu = band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
-  const long long nstrips = (p->nx + kStripW - 1) / kStripW;
+  const long long nstrips = (p->nx + 8 + kStripW - 1) / kStripW;
   // segments per strip that keep every wave resident: ceil(ny / h) * nstrips <= slots
   const long long segs = std::max<long long>(1, slots / nstrips);
   long long h = (p->ny + segs - 1) / segs;
@@ -129,9 +129,45 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
   return SPIDER_OK;
 }
 
-// Enqueue the whole time loop: buffers b_0 = in, b_1 .. b_steps with b_steps = out,
-// alternating between out and the plan's scratch so that the last step lands in
-// out and `in` is never written (unless in == out).
+spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
+  BandGrid g = p->grid_tb2;
+  g.in = src;
+  g.out = dst;
+  hipError_t e = launch_band2d_tb2(p->r, p->operand, p->engine, g, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SPIDER_OK;
+}
+
+void set_tile2(spider_plan_s* p, int h) {
+  p->tile_h2 = h;
+  p->grid_tb2.seg_h = h;
+  p->grid_tb2.nsegs_y = (p->ny + h - 1) / h;
+  p->grid_tb2.nblocks = p->grid_tb2.nstrips * p->grid_tb2.nsegs_y;
+}
+
+// Segment height of the two-step kernel: one resident round, at least 32 rows
+// (its halo is 4r lines).
+static int auto_tile_h_tb2(const spider_plan_s* p) {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  int per_cu = band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine);
+  if (per_cu <= 0) per_cu = 8;
+  const long long slots = (long long)ncu * per_cu;
+  const long long nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;
+  const long long segs = std::max<long long>(1, slots / nstrips);
+  long long h = (p->ny + segs - 1) / segs;
+  h = std::max<long long>(h, 32);
+  h = std::min<long long>(h, p->ny);
+  return (int)h;
+}
+
+// Enqueue the whole time loop as launches of 1 or 2 steps each: buffers b_0 = in,
+// b_1 .. b_L (L launches) with b_L = out, alternating between out and the plan's
+// scratch so that the last launch lands in out and `in` is never written (unless
+// in == out).
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s) {
   const size_t bytes = p->grid_bytes;
   if (steps == 0) {
@@ -141,19 +177,20 @@ spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int ste
     }
     return SPIDER_OK;
   }
+  const int pairs = p->time_block == 2 ? steps / 2 : 0;
+  const int launches = pairs + (steps - 2 * pairs);
   const void* src = in;
-  // b_k = out if (steps - k) is even, else scratch.  With in == out and b_1 == out
-  // (steps odd), step 1 would read and write one buffer: copy in to scratch first.
-  if (in == out && (steps - 1) % 2 == 0) {
+  // b_k = out if (L - k) is even, else scratch.  With in == out and b_1 == out
+  // (L odd), launch 1 would read and write one buffer: copy in to scratch first.
+  if (in == out && (launches - 1) % 2 == 0) {
     hipError_t e = hipMemcpyAsync(p->d_scratch, in, bytes, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     src = p->d_scratch;
-    // now b_1 = out differs from src = scratch, and later steps alternate as usual
   }
-  for (int k = 1; k <= steps; ++k) {
-    void* dst = ((steps - k) % 2 == 0) ? out : p->d_scratch;
-    if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: step %d reads and writes one buffer", k);
-    spider_status st = launch_step(p, src, dst, s);
+  for (int k = 1; k <= launches; ++k) {
+    void* dst = ((launches - k) % 2 == 0) ? out : p->d_scratch;
+    if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: launch %d reads and writes one buffer", k);
+    spider_status st = (k <= pairs) ? launch_step2(p, src, dst, s) : launch_step(p, src, dst, s);
     if (st != SPIDER_OK) return st;
     src = dst;
   }
@@ -178,6 +215,8 @@ spider_status spider_opts_default(spider_opts* o) {
   o->split = 2;
   o->tile_h = 0;
   o->use_graph = 1;
+  o->autotune = 0;
+  o->time_block = 0;
   return SPIDER_OK;
 }
 
@@ -212,6 +251,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   if (engine != SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 1)
     return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines: 3-D radius 1 only in this build");
   if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
+  if (o.time_block < 0 || o.time_block > 2) return fail(SPIDER_ERR_INVALID, "time_block must be 0, 1 or 2");
 
   auto* p = new spider_plan_s();
   p->ndim = ndim;
@@ -301,7 +341,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     g.ny = p->ny;
     g.nx = p->nx;
     g.seg_h = p->tile_h;
-    g.nstrips = (p->nx + kStripW - 1) / kStripW;
+    g.nstrips = ndim == 2 ? (p->nx + 8 + kStripW - 1) / kStripW : (p->nx + kStripW - 1) / kStripW;
     g.apack = static_cast<const uint4*>(p->d_apack);
     g.ipack = static_cast<const uint32_t*>(p->d_ipack);
     g.dpack = static_cast<const uint4*>(p->d_dpack);
@@ -314,6 +354,14 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       g.nsegs_z = (p->nz + p->tile_h - 1) / p->tile_h;
     }
     g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
+    // two fused steps per launch: 2-D, radius <= 3
+    const bool tb2_ok = ndim == 2 && radius <= 3;
+    p->time_block = (o.time_block != 1 && tb2_ok) ? 2 : 1;
+    if (p->time_block == 2) {
+      p->grid_tb2 = g;
+      p->grid_tb2.nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;
+      set_tile2(p, o.tile_h ? o.tile_h : auto_tile_h_tb2(p));
+    }
   }
   if (o.autotune && o.tile_h == 0) {
     spider_status st = ensure_scratch(p);
@@ -386,7 +434,7 @@ spider_status spider_plan_destroy(spider_plan_t p) {
 }
 
 spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* tile_h, int* nrows_nonzero,
-                               size_t* scratch_bytes) {
+                               size_t* scratch_bytes, int* time_block, int* tile_h2) {
   clear_err();
   if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
   if (engine) *engine = p->engine;
@@ -402,6 +450,8 @@ spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* ti
     *nrows_nonzero = n;
   }
   if (scratch_bytes) *scratch_bytes = p->grid_bytes;
+  if (time_block) *time_block = p->engine == SPIDER_ENGINE_DIRECT ? 1 : p->time_block;
+  if (tile_h2) *tile_h2 = p->time_block == 2 ? p->tile_h2 : 0;
   return SPIDER_OK;
 }
 

@@ -271,3 +271,42 @@ def test_full_size_box3d27p_sampled(oracle_mod):
         g.append(got[p])
     rms, mx = rel_errors(np.array(g), np.array(ref))
     assert rms <= 2e-3 and mx <= 1e-2, (rms, mx)
+
+
+# ------------------------------------------------------------------ two fused steps per launch
+
+@pytest.mark.parametrize("carry", ["f16", "bf16"])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("shape", [(300, 520), (77, 301), (1, 1), (5, 8), (260, 1032), (41, 241), (129, 480)])
+def test_time_block_bitwise_equals_single_steps(carry, engine, shape):
+    import torch
+    rng = np.random.default_rng(shape[0] * 7 + shape[1])
+    for kind, r in [("box", 1), ("box", 2), ("box", 3), ("star", 3)]:
+        w = np.zeros((2 * r + 1, 2 * r + 1))
+        m = si.shape_mask(2, r, kind)
+        w[m] = rng.uniform(-1, 1, int(m.sum()))
+        w /= np.abs(w).sum()
+        xd, _ = to_dev(rng.uniform(-1, 1, shape), carry)
+        p1 = sp.Plan(w, shape, carry=carry, engine=engine, time_block=1)
+        p2 = sp.Plan(w, shape, carry=carry, engine=engine, time_block=2)
+        for steps in (1, 2, 3, 4, 7):
+            a, b = torch.empty_like(xd), torch.empty_like(xd)
+            p1.apply(xd, a, steps)
+            p2.apply(xd, b, steps)
+            assert torch.equal(a, b), (kind, r, steps)
+
+
+def test_time_block_tile_heights_and_aliasing(oracle_mod):
+    import torch
+    shape = (130, 600)
+    w = si.integer_coeffs(2, 3, -1, 1, 5, "star")   # 2 steps: |v| <= 13 * 13 * 2, exact in fp16
+    xd, x64 = to_dev(si.grid_integer(shape, -2, 2, 6), "f16")
+    ref = oracle_mod.apply(w, x64, 2)
+    for th in (1, 5, 16, 33, 200):
+        p = sp.Plan(w, shape, carry="f16", tile_h=th, time_block=2)
+        y = torch.empty_like(xd)
+        p.apply(xd, y, 2)
+        assert np.array_equal(from_dev(y), ref), th
+        z = xd.clone()
+        p.apply(z, z, 2)
+        assert np.array_equal(from_dev(z), ref), th
