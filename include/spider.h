@@ -53,7 +53,8 @@ typedef enum { SPIDER_F64 = 0, SPIDER_F32 = 1, SPIDER_F16 = 2, SPIDER_BF16 = 3 }
 
 typedef enum {
     SPIDER_ENGINE_AUTO = 0,   /* sparse for 16-bit carries, direct otherwise */
-    SPIDER_ENGINE_SPARSE = 1, /* strided swap + v_smfmac (16-bit operands only) */
+    SPIDER_ENGINE_SPARSE = 1, /* strided swap + v_smfmac on 16-bit operands; the carry is the
+                                 operand type, or fp32 (2-D) with operands split from it */
     SPIDER_ENGINE_DENSE = 2,  /* same band and gather on dense v_mfma (16-bit operands) */
     SPIDER_ENGINE_DIRECT = 3  /* plain neighbour sum on the vector ALUs (fp32 / fp64 carries) */
 } spider_engine;
@@ -62,8 +63,11 @@ typedef enum {
 typedef struct {
     int carry;     /* spider_dtype of the grids passed to apply (default SPIDER_F16) */
     int engine;    /* spider_engine (default AUTO) */
-    int split;     /* coefficient split for 16-bit operands: 1 = w rounded once,
-                      2 = w_hi + w_lo (default); ignored by the direct engine */
+    int split;     /* products on the matrix engines (ignored by the direct engine):
+                      1 = w rounded once to the operand type,
+                      2 = w_hi + w_lo, each rounded (default),
+                      3 = fp32 carry only: also splits every input value x = x_hi + x_lo
+                          and adds the products with x_lo (two instructions per kernel row) */
     int tile_h;    /* output rows per wavefront segment, 0 = chosen by the autotuner */
     int use_graph; /* 1 = capture each (in, out, steps) time loop once as a hipGraph and
                       replay it (default), 0 = launch every step */
@@ -71,9 +75,12 @@ typedef struct {
                       plan time and keep the fastest (results cached per shape, radius,
                       engine and dtype for the life of the process); 0 = occupancy heuristic */
     int time_block; /* time steps fused per launch: 0 = automatic (two for 2-D grids of
-                       radius <= 3 on the matrix engines, else one), 1 = one step per launch,
-                       2 = two where supported.  Results are identical bit for bit. */
-    int reserved[1];
+                       radius <= 3 on the matrix engines with a 16-bit carry, else one),
+                       1 = one step per launch, 2 = two where supported.  Results are
+                       identical bit for bit. */
+    int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16
+                      (default, also when 0) or SPIDER_BF16.  With a 16-bit carry the operand
+                      is the carry type and this field must be 0 or equal to it. */
 } spider_opts;
 
 typedef struct spider_plan_s* spider_plan_t;
@@ -96,8 +103,9 @@ spider_status spider_opts_default(spider_opts* o);
  * to 2:4 values + 2-bit indices and packs them in the gfx950 lane order and uploads
  * them to the current HIP device.  A grid-sized scratch buffer is allocated on the
  * first spider_apply / spider_apply_batch (or at plan time when autotuning).
- * Errors: INVALID (arguments), UNSUPPORTED (e.g. sparse engine with an fp32/fp64
- * carry), OOM, HIP.  The plan is immutable after creation and owns its device memory.
+ * Errors: INVALID (arguments), UNSUPPORTED (e.g. a matrix engine with an fp64 carry,
+ * or with an fp32 carry on a 3-D grid), OOM, HIP.  The plan is immutable after
+ * creation and owns its device memory.
  */
 spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, int radius,
                           const spider_opts* opts, spider_plan_t* out);

@@ -33,7 +33,7 @@ class SpiderError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("carry", ctypes.c_int), ("engine", ctypes.c_int), ("split", ctypes.c_int),
                 ("tile_h", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("time_block", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
+                ("time_block", ctypes.c_int), ("operand", ctypes.c_int)]
 
 
 _lib = None
@@ -147,10 +147,11 @@ def _stream_handle(stream):
 
 class Plan:
     """A stencil plan: coefficients (2r+1,)*ndim (w[dz][dy][dx] multiplies x[p + offset]),
-    grid shape, carry dtype and engine.  Owns device memory until `close()`."""
+    grid shape, carry dtype and engine.  `operand` ("f16"/"bf16") selects the 16-bit
+    operand type of the matrix engines for an "f32" carry.  Owns device memory until `close()`."""
 
     def __init__(self, coeffs, shape, carry="f16", engine="auto", split=2, tile_h=0, use_graph=True, autotune=False,
-                 time_block=0):
+                 time_block=0, operand=None):
         w = np.ascontiguousarray(coeffs, dtype=np.float64)
         ndim = len(shape)
         if w.ndim != ndim or len(set(w.shape)) != 1 or w.shape[0] % 2 != 1:
@@ -167,6 +168,7 @@ class Plan:
         opts.use_graph = 1 if use_graph else 0
         opts.autotune = 1 if autotune else 0
         opts.time_block = int(time_block)
+        opts.operand = DTYPES[operand] if operand else 0
         shp = (ctypes.c_int64 * ndim)(*self.shape)
         h = ctypes.c_void_p()
         _check(lib().spider_plan(_ptr(w), ndim, shp, self.radius, ctypes.byref(opts), ctypes.byref(h)))

@@ -35,6 +35,7 @@ struct spider_plan_s {
   int time_block = 1;                   // steps fused per launch of the matrix engines (1 or 2)
   int tile_h2 = 0;                      // segment height of the two-step kernel
   spider_impl::BandGrid grid_tb2{};     // two-step kernel: 240-wide strips
+  spider_impl::BandGrid grid_batch{};   // one-step kernel inside batched launches (taller segments)
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
   std::mutex mu;

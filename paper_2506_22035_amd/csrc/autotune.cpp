@@ -27,7 +27,8 @@ std::map<Key, int> g_cache;
 std::map<Key, int> g_cache2;  // two-step kernel
 
 Key key_of(const spider_plan_s* p) {
-  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine, p->rowmask, p->has_zero_tap);
+  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine * 8 + p->split, p->rowmask,
+             p->has_zero_tap);
 }
 
 void set_tile(spider_plan_s* p, int h) {

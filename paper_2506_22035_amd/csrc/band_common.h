@@ -58,11 +58,30 @@ __device__ __forceinline__ void band_gather_offsets(int lane, int* p1, int* p2) 
 // zero halo, with no per-lane branch.
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t line_rsrc(const void* base, size_t line_elems_offset, int nx,
-                                                           bool valid, int elem_bytes) {
-  const char* p = static_cast<const char*>(base) + (valid ? line_elems_offset * elem_bytes : 0);
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(p), (short)0, valid ? nx * elem_bytes : 0, kRsrcWord3);
-}
+// Sequential walk over consecutive lines of a grid (a stream of loads or of
+// stores).  next() returns the resource of the current line and advances one
+// line; only lines in [lo, hi) get a non-zero size.  Keeping the line address
+// as a running sum costs one 64-bit add per line instead of a 64-bit multiply
+// and several selects.
+struct LineWalk {
+  uint64_t addr;   // byte address of the current line (only used when it is valid)
+  int rel;         // current line - lo
+  uint32_t span;   // hi - lo, or 0
+  int nbytes;      // bytes per line
+  __device__ __forceinline__ LineWalk(const void* base, int y, int lo, int hi, int nbytes_)
+      : addr(reinterpret_cast<uint64_t>(base) + (int64_t)y * nbytes_),
+        rel(y - lo),
+        span(hi > lo ? (uint32_t)(hi - lo) : 0u),
+        nbytes(nbytes_) {}
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t next() {
+    const bool v = (uint32_t)rel < span;
+    __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(addr), (short)0, v ? nbytes : 0, kRsrcWord3);
+    addr += (uint64_t)(int64_t)nbytes;
+    ++rel;
+    return rs;
+  }
+};
 
 // Byte offset of this lane's 16-byte chunk within a staged line (strip at x0):
 // chunk c = lane covers x in [x0 - 8 + 8c, x0 + 8c); lanes >= 34 get an
@@ -104,20 +123,31 @@ __device__ __forceinline__ void store_chunk_lds(uint32_t* lds, int off, u32x4 v)
 }
 
 // Convert an fp32 accumulator (4 consecutive x of one output line) to the
-// 16-bit carry, rounding to nearest even.
+// 16-bit carry, rounding to nearest even (two packed conversions).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <int OP>
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  if constexpr (OP == 2)
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, f16x2));
+  else
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+// The two fp32 values of a packed 16-bit pair (exact).
+template <int OP>
+__device__ __forceinline__ f32x2 unpack2(uint32_t w) {
+  if constexpr (OP == 2)
+    return __builtin_convertvector(__builtin_bit_cast(f16x2, w), f32x2);
+  else
+    return __builtin_convertvector(__builtin_bit_cast(bf16x2, w), f32x2);
+}
+
 template <int OP>
 __device__ __forceinline__ uint2 pack_out(f32x4 a) {
-  uint32_t w0, w1;
-  if constexpr (OP == 2) {
-    _Float16 h0 = (_Float16)a[0], h1 = (_Float16)a[1], h2 = (_Float16)a[2], h3 = (_Float16)a[3];
-    w0 = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-    w1 = (uint32_t)__builtin_bit_cast(uint16_t, h2) | ((uint32_t)__builtin_bit_cast(uint16_t, h3) << 16);
-  } else {
-    __bf16 h0 = (__bf16)a[0], h1 = (__bf16)a[1], h2 = (__bf16)a[2], h3 = (__bf16)a[3];
-    w0 = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
-    w1 = (uint32_t)__builtin_bit_cast(uint16_t, h2) | ((uint32_t)__builtin_bit_cast(uint16_t, h3) << 16);
-  }
-  return make_uint2(w0, w1);
+  return make_uint2(pack2<OP>(a[0], a[1]), pack2<OP>(a[2], a[3]));
 }
 
 // Byte offset of this lane's 4 outputs (x = x0 + 16 n + 4 h) within an output line.

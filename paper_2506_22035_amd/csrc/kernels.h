@@ -41,6 +41,12 @@ constexpr int kStripW2_host = 240;
 hipError_t launch_band2d_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
 int band2d_tb2_blocks_per_cu(int r, int operand, int engine);
 
+// One time step of the 2-D band engine on an fp32 grid: 16-bit operands are split
+// from the fp32 values on load (x_hi, and x_lo when `xlo`), results are stored as
+// fp32.  Same strips and segments as launch_band2d.
+hipError_t launch_band2d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s);
+int band2d_f32_blocks_per_cu(int r, int operand, int engine, bool xlo);
+
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
 int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);

@@ -80,13 +80,13 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
   // rows (loaded during the previous body) into U LDS rows, then issues the loads
   // of the next body, then gathers and multiplies row by row.  Input row j is
   // y = y0 - R + j; stg[q] holds row j with j % U == q.
+  // input lines y0 - R .. y0 + hrows + R - 1 are loaded in stream order; output
+  // lines are stored in order starting from the (discarded) line y0 - 2R
+  LineWalk lin(g.in, in_row(0), max(0, y0 - R), min(ny, y0 + hrows + R), nx * 2);
+  LineWalk lout(g.out, out_row(-2 * R), y0, y0 + hrows, nx * 2);
   u32x4 stg[U];
 #pragma unroll
-  for (int q = 0; q < U; ++q) {
-    const int y = in_row(q);
-    const bool valid = q < hrows + 2 * R && y >= 0 && y < ny;
-    stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
-  }
+  for (int q = 0; q < U; ++q) stg[q] = load_chunk<ALIGNED>(lin.next(), lvoff);
   f32x4 acc[RR];
 #pragma unroll
   for (int s = 0; s < RR; ++s) acc[s] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -101,19 +101,10 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
     for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
     if (jb > 0) {
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int i = jb - U + q - 2 * R;
-        const bool ovalid = i >= 0 && i < hrows;
-        store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i) * nx, nx, ovalid, 2), ovoff, done[q]);
-      }
+      for (int q = 0; q < U; ++q) store_packed<ALIGNED>(lout.next(), ovoff, done[q]);  // output jb - U + q - 2R
     }
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int jn = jb + U + q;
-      const int y = in_row(jn);
-      const bool valid = jn < hrows + 2 * R && y >= 0 && y < ny;
-      stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
-    }
+    for (int q = 0; q < U; ++q) stg[q] = load_chunk<ALIGNED>(lin.next(), lvoff);  // input jb + U + q
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < U; ++q) {
@@ -136,11 +127,7 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
     }
   }
 #pragma unroll
-  for (int q = 0; q < U; ++q) {
-    const int i = nin - U + q - 2 * R;
-    const bool ovalid = i >= 0 && i < hrows;
-    store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i) * nx, nx, ovalid, 2), ovoff, done[q]);
-  }
+  for (int q = 0; q < U; ++q) store_packed<ALIGNED>(lout.next(), ovoff, done[q]);  // output nin - U + q - 2R
 }
 
 
@@ -167,18 +154,6 @@ void band2d_kernel(BandGrid g) {
 // The result equals two single-step launches bit for bit.
 constexpr int kStripW2 = 240;
 
-template <int OP>
-__device__ __forceinline__ uint2 pack_masked(f32x4 a, bool row_ok, int x, int nx) {
-  uint2 w = pack_out<OP>(a);
-  // lane's 4 values are x .. x+3; zero those outside the grid
-  uint32_t m0 = 0, m1 = 0;
-  if (row_ok) {
-    m0 = (x >= 0 && x < nx ? 0x0000ffffu : 0u) | (x + 1 >= 0 && x + 1 < nx ? 0xffff0000u : 0u);
-    m1 = (x + 2 >= 0 && x + 2 < nx ? 0x0000ffffu : 0u) | (x + 3 >= 0 && x + 3 < nx ? 0xffff0000u : 0u);
-  }
-  return make_uint2(w.x & m0, w.y & m1);
-}
-
 template <int R, int OP, int ENG, bool ALIGNED>
 __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int RR = 2 * R + 1;
@@ -188,7 +163,9 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
   const int x0 = strip * kStripW2;
   const int y0 = seg * g.seg_h;
   const int hrows = min(g.seg_h, g.ny - y0);
-  const int nin = ((hrows + 4 * R + U - 1) / U) * U;  // input lines streamed, padded to U
+  // The second pass runs one line behind the first (software pipelining), so the
+  // stream is one line longer: output i2 completes after input line i2 + 4R + 1.
+  const int nin = ((hrows + 4 * R + 1 + U - 1) / U) * U;
   const int nx = g.nx, ny = g.ny;
   auto in_row = [&](int j) { return y0 - 2 * R + j; };
   auto mid_row = [&](int i1) { return y0 - R + i1; };
@@ -216,25 +193,23 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
   const uint32_t lvoff = chunk_voffset(x0 - 8, lane);       // staged line covers [x0 - 16, x0 + 256)
   const int xl = x0 - 8 + 16 * (lane & 15) + 4 * (lane >> 4);  // this lane's 4 outputs of either pass
   const uint32_t ovoff = (xl >= x0 && xl < x0 + kStripW2) ? (uint32_t)(xl * 2) : 0x7ffffff0u;
+  // 16-bit lanes of the packed intermediate values that lie inside the grid (zero halo)
+  const uint32_t xm0 = (xl >= 0 && xl < nx ? 0x0000ffffu : 0u) | (xl + 1 >= 0 && xl + 1 < nx ? 0xffff0000u : 0u);
+  const uint32_t xm1 = (xl + 2 >= 0 && xl + 2 < nx ? 0x0000ffffu : 0u) | (xl + 3 >= 0 && xl + 3 < nx ? 0xffff0000u : 0u);
   const int lw = chunk_lds_offset(lane, U * kLdsRowDw + 2 * kLdsRowDw);
   const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
-  // second-pass LDS lines (two, alternating): this lane's 4 values sit at dword unit 4 + 8n + 2h
+  // intermediate LDS lines (two, alternating): this lane's 4 values sit at dword unit 4 + 8n + 2h
   uint32_t* mid = lds + U * kLdsRowDw;
   const int mw = lds_phys(4 + 8 * (lane & 15) + 2 * (lane >> 4));
-  // the 8 columns left of x0 - 8 and right of x0 + 248 are never computed: keep them zero
-  if (lane < 8) {
-    const int u = (lane & 3) + (lane < 4 ? 0 : 132);
-    mid[lds_phys(u)] = 0u;
-    mid[kLdsRowDw + lds_phys(u)] = 0u;
-  }
+  // Both intermediate lines start as zero: the 8 columns outside [x0 - 8, x0 + 248) are
+  // never written, and the first iteration reads a line no pass has produced yet.
+  for (int i = lane; i < 2 * kLdsRowDw; i += 64) mid[i] = 0u;
 
+  LineWalk lin(g.in, in_row(0), max(0, y0 - 2 * R), min(ny, y0 + hrows + 2 * R), nx * 2);
+  LineWalk lout(g.out, out_row(-4 * R - 1), y0, y0 + hrows, nx * 2);
   u32x4 stg[U];
 #pragma unroll
-  for (int q = 0; q < U; ++q) {
-    const int y = in_row(q);
-    const bool valid = q < hrows + 4 * R && y >= 0 && y < ny;
-    stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
-  }
+  for (int q = 0; q < U; ++q) stg[q] = load_chunk<ALIGNED>(lin.next(), lvoff);
   f32x4 acc1[RR], acc2[RR];
 #pragma unroll
   for (int s = 0; s < RR; ++s) acc1[s] = acc2[s] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -246,25 +221,20 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
     for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
     if (jb > 0) {
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int i2 = jb - U + q - 4 * R;
-        const bool ovalid = i2 >= 0 && i2 < hrows;
-        store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i2) * nx, nx, ovalid, 2), ovoff, done[q]);
-      }
+      for (int q = 0; q < U; ++q) store_packed<ALIGNED>(lout.next(), ovoff, done[q]);  // output jb - U + q - 4R - 1
     }
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int jn = jb + U + q;
-      const int y = in_row(jn);
-      const bool valid = jn < hrows + 4 * R && y >= 0 && y < ny;
-      stg[q] = load_chunk<ALIGNED>(line_rsrc(g.in, (size_t)y * nx, nx, valid, 2), lvoff);
-    }
-    wave_lds_sync();
+    for (int q = 0; q < U; ++q) stg[q] = load_chunk<ALIGNED>(lin.next(), lvoff);  // input jb + U + q
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int j = jb + q;
+      wave_lds_sync();  // the intermediate line written last iteration is visible
       const uint32_t* lrow = lds + q * kLdsRowDw;
+      uint32_t* mprev = mid + ((j + 1) & 1) * kLdsRowDw;  // line i1 = j - 1 - 2R
+      uint32_t* mcur = mid + (j & 1) * kLdsRowDw;         // line i1 = j - 2R (written below)
       const u32x4 b = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+      const u32x4 b2 = {mprev[p1], mprev[p1 + 10], mprev[p2], mprev[p2 + 10]};
+      // first pass: input line j feeds intermediate line j - a
 #pragma unroll
       for (int a = 0; a < RR; ++a) {
         const int slot = ((q - a) % RR + RR) % RR;
@@ -273,41 +243,37 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
         else
           acc1[slot] = band_mma<OP, ENG, 0>(acc1[slot], A[a], Dh[a], Dl[a], I[a / 2], b);
       }
-      // first-pass line i1 = j - 2R is complete: it is step s+1 at mid_row(i1)
-      const int fs1 = (q + 1) % RR;
-      const int i1 = j - 2 * R;
-      const int ym = mid_row(i1);
-      const uint2 mv = pack_masked<OP>(acc1[fs1], i1 >= 0 && ym >= 0 && ym < ny, xl, nx);
-      acc1[fs1] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      uint32_t* mrow = mid + (j & 1) * kLdsRowDw;
-      *reinterpret_cast<uint2*>(mrow + mw) = mv;
-      wave_lds_sync();
-      const u32x4 b2 = {mrow[p1], mrow[p1 + 10], mrow[p2], mrow[p2 + 10]};
-      // mid line i1 feeds second-pass output i2 = i1 - a: slot (q - 2R - a) mod RR
+      // second pass: intermediate line i1 = j - 1 - 2R feeds output i2 = i1 - a,
+      // slot (j - 1 - 2R - a) mod RR = (q - a) mod RR
 #pragma unroll
       for (int a = 0; a < RR; ++a) {
-        const int slot = ((q + 1 - a) % RR + RR) % RR;
+        const int slot = ((q - a) % RR + RR) % RR;
         if (a & 1)
           acc2[slot] = band_mma<OP, ENG, 1>(acc2[slot], A[a], Dh[a], Dl[a], I[a / 2], b2);
         else
           acc2[slot] = band_mma<OP, ENG, 0>(acc2[slot], A[a], Dh[a], Dl[a], I[a / 2], b2);
       }
-      // second-pass output i2 = j - 4R is complete
-      const int fs2 = (q + 2) % RR;
-      done[q] = pack_out<OP>(acc2[fs2]);
-      acc2[fs2] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      // output i2 = j - 1 - 4R is complete: slot (q - 2R) mod RR = (q + 1) mod RR
+      const int fs = (q + 1) % RR;
+      done[q] = pack_out<OP>(acc2[fs]);
+      acc2[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      // intermediate line i1 = j - 2R is complete (same slot): round it like a stored
+      // step, zero it outside the grid, and leave it for the next iteration
+      const int i1 = j - 2 * R;
+      const int ym = mid_row(i1);
+      const uint2 pv = pack_out<OP>(acc1[fs]);
+      const bool rok = i1 >= 0 && ym >= 0 && ym < ny;
+      *reinterpret_cast<uint2*>(mcur + mw) = make_uint2(rok ? (pv.x & xm0) : 0u, rok ? (pv.y & xm1) : 0u);
+      acc1[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
   }
 #pragma unroll
-  for (int q = 0; q < U; ++q) {
-    const int i2 = nin - U + q - 4 * R;
-    const bool ovalid = i2 >= 0 && i2 < hrows;
-    store_packed<ALIGNED>(line_rsrc(g.out, (size_t)out_row(i2) * nx, nx, ovalid, 2), ovoff, done[q]);
-  }
+  for (int q = 0; q < U; ++q) store_packed<ALIGNED>(lout.next(), ovoff, done[q]);  // output nin - U + q - 4R - 1
 }
 
 template <int R, int OP, int ENG, bool ALIGNED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void band2d_tb2_kernel(BandGrid g) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3 : 2))) void band2d_tb2_kernel(
+    BandGrid g) {
   constexpr int RR = 2 * R + 1;
   constexpr int U = (RR >= 5) ? RR : 2 * RR;
   __shared__ uint32_t lds[U * kLdsRowDw + 2 * kLdsRowDw + kLdsSpareDw];
@@ -439,19 +405,40 @@ __device__ __forceinline__ void band3d_body(const BandGrid& g, int w, uint32_t* 
   const int lw = chunk_lds_offset(lane, NL * kLdsRowDw);
   const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
 
-  // plane pj is z = z0 - R + pj; stg holds its NL lines (y = yb0 - R + l)
+  // Planes are staged in order: plane pj is z = z0 - R + pj, and stg holds its NL
+  // lines y = yb0 - R + l.  Wanted planes: z in [z0 - R, z0 + hz + R) inside the grid.
+  const int lb = nx * 2;
+  const int64_t pbytes = (int64_t)ny * lb;
+  uint64_t in_addr = reinterpret_cast<uint64_t>(g.in) + ((int64_t)(z0 - R) * ny + (yb0 - R)) * lb;
+  const int zlo = max(0, z0 - R), zhi = min(nz, z0 + hz + R);
+  int zrel = z0 - R - zlo;
+  const uint32_t zspan = zhi > zlo ? (uint32_t)(zhi - zlo) : 0u;
   u32x4 stg[NL];
-  auto stage = [&](int pj) {
-    const int z = z0 - R + pj;
-    const bool zvalid = pj < hz + 2 * R && z >= 0 && z < nz;
+  auto stage = [&]() {
+    const bool zv = (uint32_t)zrel < zspan;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      const int y = yb0 - R + l;
-      const bool valid = zvalid && y >= 0 && y < ny;
-      stg[l] = load_chunk<ALIGNED>(line_rsrc(g.in, ((size_t)z * ny + y) * nx, nx, valid, 2), lvoff);
+      const bool valid = zv && (uint32_t)(yb0 - R + l) < (uint32_t)ny;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          reinterpret_cast<void*>(in_addr + (uint64_t)(l * lb)), (short)0, valid ? lb : 0, kRsrcWord3);
+      stg[l] = load_chunk<ALIGNED>(rs, lvoff);
     }
+    in_addr += (uint64_t)pbytes;
+    ++zrel;
   };
-  stage(0);
+  // Output planes are stored in order, plane k = z0 + k, lines yb0 + b.
+  uint64_t out_addr = reinterpret_cast<uint64_t>(g.out) + ((int64_t)z0 * ny + yb0) * lb;
+  auto store_plane = [&](int k, const uint2* vals) {
+#pragma unroll
+    for (int b = 0; b < YB; ++b) {
+      const bool ov = k < hz && yb0 + b < ny;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          reinterpret_cast<void*>(out_addr + (uint64_t)(b * lb)), (short)0, ov ? lb : 0, kRsrcWord3);
+      store_packed<ALIGNED>(rs, ovoff, vals[b]);
+    }
+    out_addr += (uint64_t)pbytes;
+  };
+  stage();
   f32x4 acc[RR][YB];
 #pragma unroll
   for (int s = 0; s < RR; ++s)
@@ -467,16 +454,8 @@ __device__ __forceinline__ void band3d_body(const BandGrid& g, int w, uint32_t* 
       wave_lds_sync();
 #pragma unroll
       for (int l = 0; l < NL; ++l) store_chunk_lds(lds, lw + l * lstride, stg[l]);
-      if (done_plane >= 0) {
-#pragma unroll
-        for (int b = 0; b < YB; ++b) {
-          const int y = yb0 + b;
-          const bool ov = done_plane < hz && y < ny;
-          store_packed<ALIGNED>(line_rsrc(g.out, ((size_t)(z0 + done_plane) * ny + y) * nx, nx, ov, 2), ovoff,
-                                done[b]);
-        }
-      }
-      stage(pj + 1);
+      if (done_plane >= 0) store_plane(done_plane, done);
+      stage();  // plane pj + 1
       wave_lds_sync();
 #pragma unroll
       for (int l = 0; l < NL; ++l) {
@@ -508,14 +487,7 @@ __device__ __forceinline__ void band3d_body(const BandGrid& g, int w, uint32_t* 
       done_plane = pj - 2 * R;
     }
   }
-  if (done_plane >= 0) {
-#pragma unroll
-    for (int b = 0; b < YB; ++b) {
-      const int y = yb0 + b;
-      const bool ov = done_plane < hz && y < ny;
-      store_packed<ALIGNED>(line_rsrc(g.out, ((size_t)(z0 + done_plane) * ny + y) * nx, nx, ov, 2), ovoff, done[b]);
-    }
-  }
+  if (done_plane >= 0) store_plane(done_plane, done);
 }
 
 template <int R, int OP, int ENG, bool ALIGNED, uint32_t MASK>

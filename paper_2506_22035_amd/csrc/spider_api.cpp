@@ -60,7 +60,8 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
+  int per_cu = p->carry == SPIDER_F32 ? band2d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3)
+                                      : band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
   const long long nstrips = (p->nx + 8 + kStripW - 1) / kStripW;
@@ -114,6 +115,11 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
   if (p->engine == SPIDER_ENGINE_DIRECT) {
     e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, p->has_zero_tap, src, dst, p->nz, p->ny, p->nx,
                       p->d_coeffs, p->tile_h, s);
+  } else if (p->ndim == 2 && p->carry == SPIDER_F32) {
+    BandGrid g = p->grid_template;
+    g.in = src;
+    g.out = dst;
+    e = launch_band2d_f32(p->r, p->operand, p->engine, p->split == 3, g, s);
   } else if (p->ndim == 2) {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -238,17 +244,24 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   const bool low = (o.carry == SPIDER_F16 || o.carry == SPIDER_BF16);
   if (engine == SPIDER_ENGINE_AUTO) engine = low ? SPIDER_ENGINE_SPARSE : SPIDER_ENGINE_DIRECT;
   if (engine < SPIDER_ENGINE_SPARSE || engine > SPIDER_ENGINE_DIRECT) return fail(SPIDER_ERR_INVALID, "bad engine");
-  if ((engine == SPIDER_ENGINE_SPARSE || engine == SPIDER_ENGINE_DENSE) && !low)
+  const bool matrix = engine != SPIDER_ENGINE_DIRECT;
+  if (o.operand != 0 && o.operand != SPIDER_F16 && o.operand != SPIDER_BF16)
+    return fail(SPIDER_ERR_INVALID, "operand must be 0, SPIDER_F16 or SPIDER_BF16");
+  if (low && o.operand != 0 && o.operand != o.carry)
+    return fail(SPIDER_ERR_INVALID, "with a 16-bit carry the operand type is the carry type");
+  if (matrix && o.carry == SPIDER_F64)
     return fail(SPIDER_ERR_UNSUPPORTED,
-                "the matrix engines take 16-bit operands (gfx950 has no fp32/fp64 structured-sparse instruction); "
-                "use the direct engine for fp32/fp64 grids");
+                "the matrix engines take 16-bit operands (gfx950 has no fp64 structured-sparse instruction); "
+                "use the direct engine for fp64 grids");
+  if (matrix && o.carry == SPIDER_F32 && ndim != 2)
+    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines with an fp32 carry: 2-D grids only in this build");
   if (engine == SPIDER_ENGINE_DIRECT && low)
     return fail(SPIDER_ERR_UNSUPPORTED, "the direct engine runs fp32/fp64 grids only");
-  if (engine != SPIDER_ENGINE_DIRECT && o.split != 1 && o.split != 2)
-    return fail(SPIDER_ERR_INVALID, "split must be 1 or 2");
+  if (matrix && (o.split < 1 || o.split > 3 || (o.split == 3 && low)))
+    return fail(SPIDER_ERR_INVALID, "split must be 1 or 2 (16-bit carry) or 1..3 (fp32 carry)");
   if (engine == SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 2)
     return fail(SPIDER_ERR_UNSUPPORTED, "direct engine: 3-D radius up to 2");
-  if (engine != SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 1)
+  if (matrix && ndim == 3 && radius > 1)
     return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines: 3-D radius 1 only in this build");
   if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
   if (o.time_block < 0 || o.time_block > 2) return fail(SPIDER_ERR_INVALID, "time_block must be 0, 1 or 2");
@@ -260,7 +273,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   p->ny = (int)shape[ndim - 2];
   p->nx = (int)shape[ndim - 1];
   p->carry = o.carry;
-  p->operand = low ? o.carry : SPIDER_F16;
+  p->operand = low ? o.carry : (o.operand ? o.operand : SPIDER_F16);
   p->engine = engine;
   p->split = o.split;
   p->use_graph = o.use_graph;
@@ -312,7 +325,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       for (int t = 0; t < kw; ++t) nz |= row[t] != 0.0;
       if (nz) mask |= 1u << i;
       std::string err;
-      if (!pack_row(row, radius, p->operand, p->split, &rows[i], &err)) {
+      if (!pack_row(row, radius, p->operand, std::min(p->split, 2), &rows[i], &err)) {
         spider_plan_destroy(p);
         return fail(SPIDER_ERR_INVALID, "%s", err.c_str());
       }
@@ -354,8 +367,21 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       g.nsegs_z = (p->nz + p->tile_h - 1) / p->tile_h;
     }
     g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
-    // two fused steps per launch: 2-D, radius <= 3
-    const bool tb2_ok = ndim == 2 && radius <= 3;
+    // Inside a batched launch the other grids fill the device, so work units can be
+    // taller than the single-launch height (their per-unit prologue and halo are
+    // amortised over more lines): at least 64 lines (2-D) or 16 planes (3-D).
+    p->grid_batch = g;
+    {
+      const int hb = ndim == 2 ? std::min(p->ny, std::max(p->tile_h, 64)) : std::min(p->nz, std::max(p->tile_h, 16));
+      p->grid_batch.seg_h = hb;
+      if (ndim == 2)
+        p->grid_batch.nsegs_y = (p->ny + hb - 1) / hb;
+      else
+        p->grid_batch.nsegs_z = (p->nz + hb - 1) / hb;
+      p->grid_batch.nblocks = p->grid_batch.nstrips * p->grid_batch.nsegs_y * p->grid_batch.nsegs_z;
+    }
+    // two fused steps per launch: 2-D, radius <= 3, 16-bit carry
+    const bool tb2_ok = ndim == 2 && radius <= 3 && low;
     p->time_block = (o.time_block != 1 && tb2_ok) ? 2 : 1;
     if (p->time_block == 2) {
       p->grid_tb2 = g;

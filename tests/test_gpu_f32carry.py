@@ -1,0 +1,163 @@
+"""GPU parity of the matrix engines with an fp32 carry (2-D).
+
+With an fp32 carry every input value is split on load into 16-bit operands
+x = x_hi + x_lo; with split 3 the kernel adds the products of the split
+coefficients with both parts.  Integer cases whose values outgrow the 16-bit
+significand (but stay exact in fp32) are therefore reproduced bit for bit over
+several steps, which pins the x_lo path.  Without the input split (split 2) the
+arithmetic is that of the 16-bit carry, so rounding the fp32 result to the
+16-bit type must give the 16-bit carry's result bit for bit.
+"""
+import numpy as np
+import pytest
+
+import paper_2506_22035_amd as sp
+import stencil_inputs as si
+from gpu_helpers import empty_like_dev, from_dev, rel_errors, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# stated tolerances (rel-RMS, rel-max) of the fp32 carry with split 3 versus the fp64 oracle
+TOL3 = {"f16": (5e-5, 5e-5), "bf16": (2e-4, 2e-4)}
+
+SHAPES = [(300, 520), (77, 301), (1, 1), (5, 8), (33, 256), (260, 1030)]
+
+
+def run(plan, x_dev, steps):
+    y = empty_like_dev(x_dev)
+    plan.apply(x_dev, y, steps)
+    return from_dev(y)
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_integer_exact_input_split(oracle_mod, operand, engine, shape):
+    # All-ones 3x3 taps on inputs in {1, 2}: the inputs of the fifth step reach ~1e4,
+    # beyond the 16-bit significand but exact as x_hi + x_lo, and the outputs (~1e5)
+    # are exact in fp32.  The other cases mix signs.
+    cases = [(np.ones((3, 3)), 5, (1, 2))]
+    cases += [(si.integer_coeffs(2, r, -1, 1, 50 + r, kind), steps, (-2, 2))
+              for kind, r, steps in [("box", 1, 4), ("star", 3, 2), ("box", 3, 2), ("box", 2, 2)]]
+    for w, steps, (lo, hi) in cases:
+        r = (w.shape[0] - 1) // 2
+        x = si.grid_integer(shape, lo, hi, 60 + shape[1])
+        xd, x64 = to_dev(x, "f32")
+        plan = sp.Plan(w, shape, carry="f32", engine=engine, split=3, operand=operand)
+        got = run(plan, xd, steps)
+        ref = oracle_mod.apply(w, x64, steps)
+        assert np.abs(oracle_mod.apply(w, x64, steps - 1)).max() < 65504
+        assert np.array_equal(got, ref), (r, steps, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+def test_without_input_split_large_values_are_rounded(oracle_mod, operand):
+    # the same growing integer case without x_lo is not exact: the split is what makes it so
+    shape = (64, 300)
+    w = np.ones((3, 3))
+    x = si.grid_integer(shape, 1, 2, 7)
+    xd, x64 = to_dev(x, "f32")
+    ref = oracle_mod.apply(w, x64, 5)
+    got2 = run(sp.Plan(w, shape, carry="f32", engine="sparse", split=2, operand=operand), xd, 5)
+    got3 = run(sp.Plan(w, shape, carry="f32", engine="sparse", split=3, operand=operand), xd, 5)
+    assert np.array_equal(got3, ref)
+    assert not np.array_equal(got2, ref)
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+def test_f32_carry_rounded_equals_16bit_carry(operand, engine):
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    x16, _ = to_dev(wl["make_grid"](), operand)
+    x32 = x16.to(torch.float32)
+    for tb in (1, 0):
+        p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, engine=engine, time_block=tb)
+        y16 = torch.empty_like(x16)
+        p16.apply(x16, y16, 9)
+        p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=2, operand=operand)
+        y32 = torch.empty_like(x32)
+        p32.apply(x32, y32, 9)
+        torch.cuda.synchronize()
+        assert torch.equal(y32.to(x16.dtype), y16), tb
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("name", ["box2d49p_10240", "star2d13p_8192"])
+def test_workload_tolerance_input_split(oracle_mod, operand, engine, name):
+    wl = si.workload(name, small=True)
+    xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=3, operand=operand)
+    got = run(plan, xd, wl["steps"])
+    rms, mx = rel_errors(got, oracle_mod.apply(wl["coeffs"], x64, wl["steps"]))
+    print("%s f32 carry, %s operands, %s: rel-RMS %.3e rel-max %.3e" % (name, operand, engine, rms, mx))
+    tr, tm = TOL3[operand]
+    assert rms <= tr and mx <= tm
+
+
+@pytest.mark.parametrize("r", [4, 5, 6, 7])
+def test_large_radius_random(oracle_mod, r):
+    rng = np.random.default_rng(r)
+    w = rng.uniform(0, 1, (2 * r + 1, 2 * r + 1))
+    w /= w.sum()
+    shape = (97, 530)
+    x = rng.uniform(0, 1, shape)
+    xd, x64 = to_dev(x, "f32")
+    for engine in ("sparse", "dense"):
+        plan = sp.Plan(w, shape, carry="f32", engine=engine, split=3)
+        rms, mx = rel_errors(run(plan, xd, 3), oracle_mod.apply(w, x64, 3))
+        assert rms <= TOL3["f16"][0] and mx <= TOL3["f16"][1], engine
+
+
+def test_tile_heights_and_aliasing(oracle_mod):
+    import torch
+    wl = si.workload("star2d13p_8192", small=True)
+    xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
+    res = []
+    for th in (0, 1, 7, 16, 50, 1000):
+        plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, tile_h=th)
+        res.append(run(plan, xd, 5))
+    for r_ in res[1:]:
+        assert np.array_equal(r_, res[0])
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3)
+    keep = xd.clone()
+    for steps in (0, 1, 2, 3):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        ref = run(plan, xd, steps)
+        assert np.array_equal(from_dev(y), ref)
+    assert torch.equal(xd, keep)
+
+
+def test_full_size_box2d49p_sampled(oracle_mod):
+    # the headline workload at full size with the fp32 carry and split 3, as the benchmark runs it
+    from test_gpu_parity import _cone_samples
+    wl = si.workload("box2d49p_10240")
+    xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3)
+    got = run(plan, xd, wl["steps"])
+    rng = np.random.default_rng(1)
+    n = wl["shape"][0]
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (7, 3000), (n // 2, n // 3)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(10)]
+    ref = _cone_samples(oracle_mod, wl["coeffs"], x64, wl["steps"], pts)
+    rms, mx = rel_errors(np.array([got[p] for p in pts]), ref)
+    print("full-size f32 carry split 3 sampled rel-RMS %.3e rel-max %.3e" % (rms, mx))
+    assert rms <= TOL3["f16"][0] and mx <= TOL3["f16"][1]
+
+
+def test_batch_and_server_reject_f32_carry():
+    import torch
+    w = np.ones((3, 3)) / 9
+    plan = sp.Plan(w, (64, 64), carry="f32", engine="sparse", split=3)
+    x = torch.zeros((64, 64), dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    with pytest.raises(sp.SpiderError) as e:
+        sp.apply_batch([plan], [x], [y], [2])
+    assert e.value.status == 2
+    srv = sp.Server(1 << 30)
+    with pytest.raises(sp.SpiderError) as e:
+        srv.submit(plan, x, y, 2)
+    assert e.value.status == 2
+    srv.close()

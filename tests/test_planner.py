@@ -260,12 +260,28 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.spider_plan(w.ctypes.data, 2, shp, 8, None, ctypes.byref(h)) == 1
     bad = (ctypes.c_int64 * 2)(0, 64)
     assert L.spider_plan(w.ctypes.data, 2, bad, 1, None, ctypes.byref(h)) == 1
-    o = sp._Opts()
-    L.spider_opts_default(ctypes.byref(o))
-    o.carry = 1
-    o.engine = 1  # sparse engine with an fp32 carry
+    def opts(**kw):
+        o = sp._Opts()
+        L.spider_opts_default(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    o = opts(carry=0, engine=1)  # sparse engine with an fp64 carry
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2
     assert "16-bit" in L.spider_last_error().decode()
+    w3 = np.ones((3, 3, 3)) / 27
+    shp3 = (ctypes.c_int64 * 3)(16, 16, 16)
+    o = opts(carry=1, engine=1, split=3)  # fp32 carry on the matrix engines: 2-D only
+    assert L.spider_plan(w3.ctypes.data, 3, shp3, 1, ctypes.byref(o), ctypes.byref(h)) == 2
+    o = opts(carry=2, engine=1, split=3)  # the input split needs an fp32 carry
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    o = opts(carry=1, engine=1, split=4)
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    o = opts(carry=2, engine=1, operand=3)  # operand must be the 16-bit carry type
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    o = opts(carry=1, engine=2, operand=1)  # operands are 16-bit
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
     assert L.spider_apply(None, None, None, 1, None) == 1
     assert L.spider_plan_destroy(None) == 0
     with pytest.raises(sp.SpiderError):
