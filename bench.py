@@ -32,7 +32,7 @@ METRIC = "GStencil/s at stated error vs FP64 oracle (vs plain GPU path); p50/p99
 TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": (5e-5, 5e-5)}
 KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band.hip", "paper_2506_22035_amd/csrc/band_common.h"]
 # the dominant kernel of the headline run: two fused time steps per launch
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_box49p_f16_10240_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_tb2_box49p_f16_10240_traffic.json")
 
 
 def kernel_source_hash():
@@ -152,6 +152,8 @@ def main():
                     help="grid dtype (default f16; f64 for box2d9p_256_f64)")
     ap.add_argument("--engine", default=None, choices=["sparse", "dense", "direct"],
                     help="default: sparse for 16-bit carries, direct otherwise")
+    ap.add_argument("--split", type=int, default=0,
+                    help="products per kernel row (default 2; 3 for an fp32 carry on a matrix engine)")
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip errors, fp32 path and ablation")
@@ -185,6 +187,8 @@ def main():
         args.carry = "f64" if args.workload == "box2d9p_256_f64" else "f16"
     if args.engine is None:
         args.engine = "sparse" if args.carry in ("f16", "bf16") else "direct"
+    if args.split == 0:
+        args.split = 3 if (args.carry == "f32" and args.engine != "direct") else 2
     headline = args.workload == "box2d49p_10240" and args.carry in ("f16", "bf16")
     T = wl["steps"]
     shape = tuple(wl["shape"])
@@ -198,8 +202,8 @@ def main():
     stream = torch.cuda.current_stream()
 
     t0 = time.perf_counter()
-    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=args.carry, engine=args.engine, tile_h=args.tile_h,
-                   autotune=True)
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=args.carry, engine=args.engine, split=args.split,
+                   tile_h=args.tile_h, autotune=True)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
 
@@ -228,7 +232,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ("direct%dd_kernel" if args.engine == "direct" else
-                       ("band%dd_tb2_kernel" if tb == 2 else "band%dd_kernel")) % len(shape)
+                       ("band%dd_tb2_kernel" if tb == 2 else
+                        ("band%dd_f32_kernel" if args.carry == "f32" else "band%dd_kernel"))) % len(shape)
                       + "<r=%d,%s,%s>" % ((wl["coeffs"].shape[0] - 1) // 2, args.carry, args.engine),
             "time_steps_per_launch": steps_per_launch,
             "alg_bytes_per_launch": alg_bytes,
@@ -253,7 +258,8 @@ def main():
            "config": {"workload": args.workload, "grid": list(shape),
                       "time_steps_per_step": T, "carry": args.carry, "operand": args.carry,
                       "accumulate": "f32" if args.carry in ("f16", "bf16") else args.carry,
-                      "engine": info["engine"], "split": 2, "tile_h": info["tile_h"],
+                      "engine": info["engine"], "split": args.split if args.engine != "direct" else None,
+                      "tile_h": info["tile_h"],
                       "time_steps_per_launch": info["time_block"], "tile_h2": info["tile_h2"],
                       "coeff_seed": wl["seeds"]["coeffs"], "grid_seed": wl["seeds"]["grid"]},
            "wall_ms_timed_region": round(wall_ms, 3), "plan_ms": round(plan_ms, 3),
