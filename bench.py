@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "GStencil/s at stated error vs FP64 oracle (vs plain GPU path); p50/p99 latency"
 TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": (5e-5, 5e-5)}
-KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band.hip", "paper_2506_22035_amd/csrc/band_common.h"]
+KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band_pair.hip", "paper_2506_22035_amd/csrc/band_pair.h",
+                  "paper_2506_22035_amd/csrc/band_common.h"]
 # the dominant kernel of the headline run: two fused time steps per launch
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_tb2_box49p_f16_10240_traffic.json")
 
@@ -155,6 +156,10 @@ def main():
     ap.add_argument("--split", type=int, default=0,
                     help="products per kernel row (default 2; 3 for an fp32 carry on a matrix engine)")
     ap.add_argument("--tile-h", type=int, default=0)
+    ap.add_argument("--band-height", type=int, default=0, choices=[0, 8, 16],
+                    help="output points per band row (0: the library's choice)")
+    ap.add_argument("--time-block", type=int, default=0, choices=[0, 1, 2],
+                    help="time steps fused per launch (0: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip errors, fp32 path and ablation")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -203,7 +208,7 @@ def main():
 
     t0 = time.perf_counter()
     plan = sp.Plan(wl["coeffs"], wl["shape"], carry=args.carry, engine=args.engine, split=args.split,
-                   tile_h=args.tile_h, autotune=True)
+                   tile_h=args.tile_h, autotune=True, band_height=args.band_height, time_block=args.time_block)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
 
@@ -232,8 +237,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ("direct%dd_kernel" if args.engine == "direct" else
-                       ("band%dd_tb2_kernel" if tb == 2 else
-                        ("band%dd_f32_kernel" if args.carry == "f32" else "band%dd_kernel"))) % len(shape)
+                       ("band%dd_f32_kernel" if args.carry == "f32" else
+                        ("band%dd_pair" if info["band_height"] == 8 else "band%dd")
+                        + ("_tb2_kernel" if tb == 2 else "_kernel"))) % len(shape)
                       + "<r=%d,%s,%s>" % ((wl["coeffs"].shape[0] - 1) // 2, args.carry, args.engine),
             "time_steps_per_launch": steps_per_launch,
             "alg_bytes_per_launch": alg_bytes,
@@ -261,6 +267,7 @@ def main():
                       "engine": info["engine"], "split": args.split if args.engine != "direct" else None,
                       "tile_h": info["tile_h"],
                       "time_steps_per_launch": info["time_block"], "tile_h2": info["tile_h2"],
+                      "band_height": info["band_height"],
                       "coeff_seed": wl["seeds"]["coeffs"], "grid_seed": wl["seeds"]["grid"]},
            "wall_ms_timed_region": round(wall_ms, 3), "plan_ms": round(plan_ms, 3),
            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),

@@ -81,6 +81,14 @@ typedef struct {
     int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16
                       (default, also when 0) or SPIDER_BF16.  With a 16-bit carry the operand
                       is the carry type and this field must be 0 or equal to it. */
+    int band_height; /* output points per band row on the matrix engines: 0 = automatic
+                        (8 where it applies, else 16), 16 = 16-point chunks with 32-column
+                        windows (any radius), 8 = the paper's band height L = 2r + 2 <= 8
+                        with two output lines per instruction (2-D, radius <= 3, 16-bit
+                        carry; segment heights are rounded up to even numbers).  The two
+                        give different rounding orders.  With band height 8 and odd r, two
+                        fused steps (time_block 2) round differently from two single
+                        steps; with band height 16 they are identical bit for bit. */
 } spider_opts;
 
 typedef struct spider_plan_s* spider_plan_t;
@@ -127,20 +135,24 @@ spider_status spider_plan_destroy(spider_plan_t plan);
 /*
  * spider_plan_info: describe a plan (host query, no device work).
  *   engine, carry, tile_h (segment height of the one-step kernel), nrows_nonzero
- *   (kernel rows on the matrix path), scratch_bytes (size of the grid-sized scratch
- *   buffer the plan allocates on first use), time_block (steps fused per launch),
- *   tile_h2 (segment height of the two-step kernel, 0 if unused).  Any output
- *   pointer may be NULL.
+ *   (kernel rows on the matrix path; for paired-line bands the r + 1 instructions
+ *   per input line pair), scratch_bytes (size of the grid-sized scratch buffer the
+ *   plan allocates on first use), time_block (steps fused per launch), tile_h2
+ *   (segment height of the two-step kernel, 0 if unused), band_height (output
+ *   points per band row: 16, or 8 for paired-line bands; 0 for the direct engine).
+ *   Any output pointer may be NULL.
  */
 spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int* tile_h,
                                int* nrows_nonzero, size_t* scratch_bytes, int* time_block,
-                               int* tile_h2);
+                               int* tile_h2, int* band_height);
 
 /*
  * Batched apply (one launch per time step over the tiles of every grid).
  * Runs grids of uneven size and stencil shape together: at time step s every
  * grid i with steps[i] > s advances by one step.  The plans must share the
  * carry dtype and use the sparse or dense engine; grids may be 2-D or 3-D.
+ * Each grid's result equals spider_apply of a plan with time_block = 1 bit for
+ * bit (and a fused plan's up to rounding, bit for bit where fusion is exact).
  *   n       number of grids, 1..4096
  *   plans, ins, outs, steps: host arrays of n entries, as for spider_apply.
  * Errors: INVALID, UNSUPPORTED (mixed carries or direct-engine plans), HIP.
@@ -226,6 +238,33 @@ spider_status spider_compress_24(const double* m, int rows, int cols, double* va
  */
 spider_status spider_pack_row(const double* row, int radius, int operand, int split, uint16_t* a_bits,
                               uint16_t* idx, uint16_t* dense_bits);
+
+/*
+ * spider_pair_gather_positions: window column of every K slot of one line's
+ * 16-slot block in the paired-line band (2-D, r <= 3; the paper's band height
+ * L = 2r + 2 rounded to 8 with two output lines stacked, Sec. 3.1.2 and Eq. 1).
+ * pos[s], s = 0..15, is a permutation of 0..15; the window of an 8-point output
+ * chunk at x0 covers input columns x0-4 .. x0+11.
+ */
+spider_status spider_pair_gather_positions(int pos[16]);
+
+/*
+ * spider_pack_pair: the packed operands of instruction k (0..r) of the
+ * paired-line band for a 2-D stencil.  w: (2r+1)^2 fp64 taps [dy][dx], r in 1..3;
+ * operand SPIDER_F16/BF16; split 1/2.  The instruction's 16 x 64 operand has row
+ * 8*phi + m (output line i + phi, point m of the chunk) and K slot
+ * 32*lambda + 16*rho + s (input line j + lambda, rho = 0 hi / 1 lo coefficient
+ * part, window column pos[s]); it holds kernel row 2k + lambda - phi, for input
+ * pairs with j - i = 2k - r.
+ *   a_bits      64 lanes x 8 16-bit values (compressed A, lane la: row la % 16,
+ *               K slots 16*(la/16) .. +15)
+ *   idx         64 lanes x 16-bit index field (2 bits per compressed value)
+ *   dense_bits  64 lanes x 16 16-bit values: K slots 8*(la/16)+e of line j (8),
+ *               then of line j + 1 (8), or NULL
+ * Errors: INVALID.
+ */
+spider_status spider_pack_pair(const double* w, int radius, int operand, int split, int k, uint16_t* a_bits,
+                               uint16_t* idx, uint16_t* dense_bits);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* spider_last_error(void);

@@ -33,7 +33,7 @@ class SpiderError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("carry", ctypes.c_int), ("engine", ctypes.c_int), ("split", ctypes.c_int),
                 ("tile_h", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("time_block", ctypes.c_int), ("operand", ctypes.c_int)]
+                ("time_block", ctypes.c_int), ("operand", ctypes.c_int), ("band_height", ctypes.c_int)]
 
 
 _lib = None
@@ -52,7 +52,7 @@ def lib():
             "spider_plan": [P, I, P, I, P, P],
             "spider_apply": [P, P, P, I, P],
             "spider_plan_destroy": [P],
-            "spider_plan_info": [P, P, P, P, P, P, P, P],
+            "spider_plan_info": [P, P, P, P, P, P, P, P, P],
             "spider_apply_batch": [I, P, P, P, P, P],
             "spider_server_create": [ctypes.c_size_t, I, I, P],
             "spider_submit": [P, P, P, P, I, P],
@@ -63,6 +63,8 @@ def lib():
             "spider_swap_columns": [I, I, P],
             "spider_compress_24": [P, I, I, P, P],
             "spider_pack_row": [P, I, I, I, P, P, P],
+            "spider_pair_gather_positions": [P],
+            "spider_pack_pair": [P, I, I, I, I, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -125,6 +127,24 @@ def pack_row(row, radius, operand="f16", split=2):
     return a, idx, dense
 
 
+def pair_gather_positions():
+    """Window column of each of the 16 K slots of a line in the paired-line band (see spider.h)."""
+    out = np.zeros(16, dtype=np.int32)
+    _check(lib().spider_pair_gather_positions(_ptr(out)))
+    return out
+
+
+def pack_pair(w, radius, k, operand="f16", split=2):
+    """Packed operands of instruction k of the paired-line band: (A bits (64, 8), index (64,), dense (64, 16))."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    a = np.zeros((64, 8), dtype=np.uint16)
+    idx = np.zeros(64, dtype=np.uint16)
+    dense = np.zeros((64, 16), dtype=np.uint16)
+    _check(lib().spider_pack_pair(_ptr(w), int(radius), DTYPES[operand], int(split), int(k), _ptr(a), _ptr(idx),
+                                  _ptr(dense)))
+    return a, idx, dense
+
+
 # ------------------------------------------------------------------ plans
 
 def _torch():
@@ -151,7 +171,7 @@ class Plan:
     operand type of the matrix engines for an "f32" carry.  Owns device memory until `close()`."""
 
     def __init__(self, coeffs, shape, carry="f16", engine="auto", split=2, tile_h=0, use_graph=True, autotune=False,
-                 time_block=0, operand=None):
+                 time_block=0, operand=None, band_height=0):
         w = np.ascontiguousarray(coeffs, dtype=np.float64)
         ndim = len(shape)
         if w.ndim != ndim or len(set(w.shape)) != 1 or w.shape[0] % 2 != 1:
@@ -169,6 +189,7 @@ class Plan:
         opts.autotune = 1 if autotune else 0
         opts.time_block = int(time_block)
         opts.operand = DTYPES[operand] if operand else 0
+        opts.band_height = int(band_height)
         shp = (ctypes.c_int64 * ndim)(*self.shape)
         h = ctypes.c_void_p()
         _check(lib().spider_plan(_ptr(w), ndim, shp, self.radius, ctypes.byref(opts), ctypes.byref(h)))
@@ -181,12 +202,14 @@ class Plan:
         return self._h
 
     def info(self):
-        e, c, t, n, tb, t2 = (ctypes.c_int() for _ in range(6))
+        e, c, t, n, tb, t2, bh = (ctypes.c_int() for _ in range(7))
         sb = ctypes.c_size_t()
         _check(lib().spider_plan_info(self.handle, ctypes.byref(e), ctypes.byref(c), ctypes.byref(t),
-                                      ctypes.byref(n), ctypes.byref(sb), ctypes.byref(tb), ctypes.byref(t2)))
+                                      ctypes.byref(n), ctypes.byref(sb), ctypes.byref(tb), ctypes.byref(t2),
+                                      ctypes.byref(bh)))
         return dict(engine=_ENGINE_NAMES[e.value], carry=_DTYPE_NAMES[c.value], tile_h=t.value,
-                    nrows_nonzero=n.value, scratch_bytes=sb.value, time_block=tb.value, tile_h2=t2.value)
+                    nrows_nonzero=n.value, scratch_bytes=sb.value, time_block=tb.value, tile_h2=t2.value,
+                    band_height=bh.value)
 
     def check_tensor(self, t):
         torch = _torch()

@@ -18,6 +18,7 @@ struct spider_plan_s {
   int operand = SPIDER_F16;  // dtype of the matrix operands (matrix engines)
   int engine = SPIDER_ENGINE_SPARSE;
   int split = 2;
+  int band_h = 16;           // output points per band row: 16, or 8 (paired-line bands)
   int tile_h = 0;
   int use_graph = 1;
   int device = 0;

@@ -27,11 +27,12 @@ std::map<Key, int> g_cache;
 std::map<Key, int> g_cache2;  // two-step kernel
 
 Key key_of(const spider_plan_s* p) {
-  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine * 8 + p->split, p->rowmask,
+  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine * 8 + p->split + 64 * p->band_h, p->rowmask,
              p->has_zero_tap);
 }
 
 void set_tile(spider_plan_s* p, int h) {
+  if (p->band_h == 8) h += h & 1;  // paired-line bands: segments start on even rows
   p->tile_h = h;
   BandGrid& g = p->grid_template;
   g.seg_h = h;

@@ -86,6 +86,7 @@ struct BatchArena {
 };
 
 static int batch_kind(const spider_plan_s* p) {
+  if (p->ndim == 2 && p->band_h == 8) return p->r == 1 ? kB2dPairR1 : (p->r == 2 ? kB2dPairR2 : kB2dPairR3);
   if (p->ndim == 2) return p->r == 1 ? kB2dR1 : (p->r == 2 ? kB2dR2 : kB2dR3);
   // 3-D r = 1: star variant when every non-zero kernel row lies on the axes cross
   const uint32_t star = (1u << 1) | (1u << 3) | (1u << 4) | (1u << 5) | (1u << 7);

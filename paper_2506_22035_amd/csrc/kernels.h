@@ -47,13 +47,31 @@ int band2d_tb2_blocks_per_cu(int r, int operand, int engine);
 hipError_t launch_band2d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s);
 int band2d_f32_blocks_per_cu(int r, int operand, int engine, bool xlo);
 
+// Paired-line band (2-D, r <= 3, 16-bit carry): 8-point chunks with a 16-column
+// window, two output lines per instruction.  Strip s covers outputs
+// [256 s - kPairWinLead, 256 s + 256 - kPairWinLead), so a grid has
+// ceil((nx + 4) / 256) strips; seg_h must be even.  Operands: R + 1 packed
+// instructions in apack / ipack / dpack (planner's pack_pair).
+constexpr int kStripWPair = 256;
+constexpr int kPairWinLead = 4;
+hipError_t launch_band2d_pair(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
+int band2d_pair_blocks_per_cu(int r, int operand, int engine);
+// Two fused steps on paired-line bands: strip s stores columns [240 s, 240 s + 240)
+// (nstrips = ceil(nx / 240)); seg_h must be even.
+constexpr int kStripWPair2 = 240;
+hipError_t launch_band2d_pair_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
+int band2d_pair_tb2_blocks_per_cu(int r, int operand, int engine);
+
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
 int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);
 
 // ------------------------------------------------------------------ batched launch
 // Body selected per grid inside the persistent batch kernel.
-enum BatchKind : int { kB2dR1 = 0, kB2dR2 = 1, kB2dR3 = 2, kB3dBox = 3, kB3dStar = 4 };
+enum BatchKind : int {
+  kB2dR1 = 0, kB2dR2 = 1, kB2dR3 = 2, kB3dBox = 3, kB3dStar = 4,
+  kB2dPairR1 = 5, kB2dPairR2 = 6, kB2dPairR3 = 7  // paired-line bands (one step)
+};
 
 // One persistent launch advancing every listed grid by one time step.
 //   grids    device array of n BandGrid (in/out already set for this step)

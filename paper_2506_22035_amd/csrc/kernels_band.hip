@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "band_common.h"
+#include "band_pair.h"
 #include "kernels.h"
 
 namespace spider_impl {
@@ -578,7 +579,9 @@ template <int OP, int ENG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void band_batch_kernel(
     const BandGrid* __restrict__ grids, const int* __restrict__ kinds, const int* __restrict__ begin, int n,
     int* __restrict__ counter) {
-  constexpr int kLds = (7 * kLdsRowDw > 6 * kLdsRowDw ? 7 * kLdsRowDw : 6 * kLdsRowDw) + kLdsSpareDw;
+  // the largest body: 16-point 2-D r = 3 (7 lines + spare) or paired r = 1 / 3 (8 lines)
+  constexpr int kLds16 = 7 * kLdsRowDw + kLdsSpareDw, kLdsPair = 8 * kPairRowDw;
+  constexpr int kLds = kLds16 > kLdsPair ? kLds16 : kLdsPair;
   __shared__ uint32_t lds[kLds];
   const int total = begin[n];
   for (;;) {
@@ -605,6 +608,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ba
         break;
       case kB2dR3:
         if (al) band2d_body<3, OP, ENG, true>(g, w, lds); else band2d_body<3, OP, ENG, false>(g, w, lds);
+        break;
+      case kB2dPairR1:
+        if (al) band2d_pair_body<1, OP, ENG, true>(g, w, lds); else band2d_pair_body<1, OP, ENG, false>(g, w, lds);
+        break;
+      case kB2dPairR2:
+        if (al) band2d_pair_body<2, OP, ENG, true>(g, w, lds); else band2d_pair_body<2, OP, ENG, false>(g, w, lds);
+        break;
+      case kB2dPairR3:
+        if (al) band2d_pair_body<3, OP, ENG, true>(g, w, lds); else band2d_pair_body<3, OP, ENG, false>(g, w, lds);
         break;
       case kB3dBox:
         if (al) band3d_body<1, OP, ENG, true, box_mask3<1>()>(g, w, lds);

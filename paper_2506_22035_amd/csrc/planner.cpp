@@ -222,4 +222,95 @@ bool pack_row(const double* row, int r, int operand, int split, PackedRow* out, 
   return true;
 }
 
+// ---------------------------------------------------------------- paired-line band
+
+// The 16 columns of a line's window form 8 32-bit pairs; 2:4 group g joins pair
+// g with pair g + 4 (8 columns apart: the strided pairing with L = 8 on pairs),
+// so a row's 2r + 1 <= 7 consecutive non-zeros never fill both pairs of a
+// group.  K slots 0..7 hold groups 0, 1 and slots 8..15 groups 3, 2: with LDS
+// chunks of 4 dwords padded to 6, lanes reading slots 0..7 and lanes reading
+// slots 8..15 then hit disjoint banks (pairs of opposite parity).
+void pair_gather_positions(int pos[kPairWin]) {
+  static const int kGroups[4] = {0, 1, 3, 2};
+  for (int q = 0; q < 4; ++q) {
+    const int g = kGroups[q];
+    for (int s = 0; s < 4; ++s) {
+      const int pair = g + (s >= 2 ? 4 : 0);
+      pos[4 * q + s] = 2 * pair + (s & 1);
+    }
+  }
+}
+
+bool pack_pair(const double* w, int r, int operand, int split, int k, PackedRow* out, std::string* err) {
+  if (!w || !out || r < 1 || r > 3 || (operand != 2 && operand != 3) || (split != 1 && split != 2) || k < 0 ||
+      k > r) {
+    if (err) *err = "pack_pair: bad arguments (r in 1..3, operand f16/bf16, split 1/2, k in 0..r)";
+    return false;
+  }
+  const int kw = 2 * r + 1;
+  double hi[49], lo[49];
+  uint16_t hib[49], lob[49];
+  for (int t = 0; t < kw * kw; ++t) {
+    hi[t] = operand == 2 ? round_f16(w[t], &hib[t]) : round_bf16(w[t], &hib[t]);
+    if (split == 2) {
+      const double rest = w[t] - hi[t];
+      lo[t] = operand == 2 ? round_f16(rest, &lob[t]) : round_bf16(rest, &lob[t]);
+    } else {
+      lo[t] = 0.0;
+      lob[t] = 0;
+    }
+  }
+  int pos[kPairWin];
+  pair_gather_positions(pos);
+  // Full 16 x 64 operand: row 8 phi + m, K slot 32 lambda + 16 rho + s.
+  double M[16][64];
+  uint16_t B[16][64];
+  for (int phi = 0; phi < 2; ++phi)
+    for (int m = 0; m < kPairM; ++m)
+      for (int lam = 0; lam < 2; ++lam)
+        for (int rho = 0; rho < 2; ++rho)
+          for (int s = 0; s < kPairWin; ++s) {
+            const int row = 2 * k + lam - phi;            // kernel row (dy + r)
+            const int t = pos[s] - kPairLead - m + r;     // tap (dx + r)
+            double v = 0.0;
+            uint16_t b = 0;
+            if (row >= 0 && row < kw && t >= 0 && t < kw) {
+              v = rho == 0 ? hi[row * kw + t] : lo[row * kw + t];
+              b = rho == 0 ? hib[row * kw + t] : lob[row * kw + t];
+            }
+            M[8 * phi + m][32 * lam + 16 * rho + s] = v;
+            B[8 * phi + m][32 * lam + 16 * rho + s] = v == 0.0 ? 0 : b;
+          }
+  double vals[16 * 32];
+  uint8_t meta[16 * 32];
+  if (!compress_24(&M[0][0], 16, 64, vals, meta)) {
+    if (err) *err = "pack_pair: band is not 2:4";
+    return false;
+  }
+  std::memset(out, 0, sizeof(*out));
+  // smfmac A: lane la = m + 16 ga holds row m, K slots 16 ga .. 16 ga + 15 (four
+  // groups); element ea is value ea % 2 of group 4 ga + ea / 2, its 2-bit position
+  // at bits 2 ea of the index field.
+  for (int la = 0; la < 64; ++la) {
+    const int m = la % 16, ga = la / 16;
+    uint16_t field = 0;
+    for (int ea = 0; ea < 8; ++ea) {
+      const int G = 4 * ga + ea / 2;
+      const int p = meta[m * 32 + 2 * G + ea % 2];
+      out->a[la * 8 + ea] = B[m][4 * G + p];
+      field |= (uint16_t)(p << (2 * ea));
+    }
+    out->idx[la] = field;
+  }
+  // dense A: lane la: row la % 16, K slots 8 (la / 16) .. + 7 of each 32-slot half
+  for (int la = 0; la < 64; ++la) {
+    const int m = la % 16;
+    for (int e = 0; e < 8; ++e) {
+      out->dense[la * 16 + e] = B[m][8 * (la / 16) + e];
+      out->dense[la * 16 + 8 + e] = B[m][32 + 8 * (la / 16) + e];
+    }
+  }
+  return true;
+}
+
 }  // namespace spider_impl

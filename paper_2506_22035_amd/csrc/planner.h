@@ -43,4 +43,23 @@ struct PackedRow {
 // operand: 2 = fp16, 3 = bf16 (spider_dtype values); split: 1 or 2.
 bool pack_row(const double* row, int r, int operand, int split, PackedRow* out, std::string* err);
 
+// Paired-line band (2-D, r <= 3): the paper's band height L = 8 >= 2r + 2 with
+// two output lines stacked in the instruction's M = 16 rows (phase 0: line i,
+// phase 1: line i + 1) and two input lines in its K = 64 (line j, then j + 1,
+// each as [hi | lo] copies of a 16-column window starting 4 columns left of
+// the 8-point chunk).  One instruction applies, for output pair (i, i + 1) and
+// input pair (j, j + 1) with j - i = -r + 2k, kernel rows 2k + lambda - phi
+// (lambda: input line of the pair, phi: phase).
+constexpr int kPairM = 8;     // outputs per line per chunk
+constexpr int kPairWin = 16;  // window columns per line
+constexpr int kPairLead = 4;  // window columns left of the chunk
+
+// pos[s] = window column held in K slot s (0..15) of a line's 16-slot block.
+void pair_gather_positions(int pos[kPairWin]);
+
+// Packed operands of instruction k (0..r) of a 2-D stencil w[(2r+1)^2] (row-major [dy][dx]).
+// a/idx: smfmac A of the 16 x 64 matrix; dense: per lane 8 values of K 0..31 (line j)
+// then 8 of K 32..63 (line j + 1), for two v_mfma_f32_16x16x32.
+bool pack_pair(const double* w, int r, int operand, int split, int k, PackedRow* out, std::string* err);
+
 }  // namespace spider_impl

@@ -60,11 +60,13 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = p->carry == SPIDER_F32 ? band2d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3)
-                                      : band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
+  int per_cu = p->band_h == 8            ? band2d_pair_blocks_per_cu(p->r, p->operand, p->engine)
+               : p->carry == SPIDER_F32 ? band2d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3)
+                                        : band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
-  const long long nstrips = (p->nx + 8 + kStripW - 1) / kStripW;
+  const long long nstrips = p->band_h == 8 ? (p->nx + kPairWinLead + kStripWPair - 1) / kStripWPair
+                                           : (p->nx + 8 + kStripW - 1) / kStripW;
   // segments per strip that keep every wave resident: ceil(ny / h) * nstrips <= slots
   const long long segs = std::max<long long>(1, slots / nstrips);
   long long h = (p->ny + segs - 1) / segs;
@@ -115,6 +117,11 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
   if (p->engine == SPIDER_ENGINE_DIRECT) {
     e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, p->has_zero_tap, src, dst, p->nz, p->ny, p->nx,
                       p->d_coeffs, p->tile_h, s);
+  } else if (p->band_h == 8) {
+    BandGrid g = p->grid_template;
+    g.in = src;
+    g.out = dst;
+    e = launch_band2d_pair(p->r, p->operand, p->engine, g, s);
   } else if (p->ndim == 2 && p->carry == SPIDER_F32) {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -139,12 +146,14 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   BandGrid g = p->grid_tb2;
   g.in = src;
   g.out = dst;
-  hipError_t e = launch_band2d_tb2(p->r, p->operand, p->engine, g, s);
+  hipError_t e = p->band_h == 8 ? launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s)
+                                : launch_band2d_tb2(p->r, p->operand, p->engine, g, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SPIDER_OK;
 }
 
 void set_tile2(spider_plan_s* p, int h) {
+  if (p->band_h == 8) h += h & 1;  // paired-line bands: segments start on even rows
   p->tile_h2 = h;
   p->grid_tb2.seg_h = h;
   p->grid_tb2.nsegs_y = (p->ny + h - 1) / h;
@@ -159,10 +168,11 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine);
+  int per_cu = p->band_h == 8 ? band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine)
+                              : band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
-  const long long nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;
+  const long long nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;  // 240 columns in both layouts
   const long long segs = std::max<long long>(1, slots / nstrips);
   long long h = (p->ny + segs - 1) / segs;
   h = std::max<long long>(h, 32);
@@ -223,6 +233,7 @@ spider_status spider_opts_default(spider_opts* o) {
   o->use_graph = 1;
   o->autotune = 0;
   o->time_block = 0;
+  o->band_height = 0;
   return SPIDER_OK;
 }
 
@@ -265,6 +276,11 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines: 3-D radius 1 only in this build");
   if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
   if (o.time_block < 0 || o.time_block > 2) return fail(SPIDER_ERR_INVALID, "time_block must be 0, 1 or 2");
+  if (o.band_height != 0 && o.band_height != 8 && o.band_height != 16)
+    return fail(SPIDER_ERR_INVALID, "band_height must be 0, 8 or 16");
+  if (o.band_height == 8 && !(matrix && ndim == 2 && radius <= 3 && low && shape[1] < (1LL << 28)))
+    return fail(SPIDER_ERR_UNSUPPORTED,
+                "band_height 8 (paired-line bands) needs a matrix engine, a 2-D grid, radius <= 3 and a 16-bit carry");
 
   auto* p = new spider_plan_s();
   p->ndim = ndim;
@@ -277,6 +293,9 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   p->engine = engine;
   p->split = o.split;
   p->use_graph = o.use_graph;
+  // paired-line bands by default where they apply (fewer instructions per output)
+  const bool pair_ok = matrix && ndim == 2 && radius <= 3 && low && shape[1] < (1LL << 28);
+  p->band_h = (o.band_height == 8 || (o.band_height == 0 && pair_ok)) ? 8 : 16;
   const int kw = 2 * radius + 1;
   const int ncoef = ndim == 2 ? kw * kw : kw * kw * kw;
   p->coeffs.assign(coeffs, coeffs + ncoef);
@@ -312,8 +331,10 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     for (double c : p->coeffs) p->has_zero_tap |= (c == 0.0);
     p->tile_h = o.tile_h ? o.tile_h : auto_tile_h_direct(p);
   } else {
-    // Offline transformation, one kernel row (line of taps along x) at a time.
-    const int nrows = ndim == 2 ? kw : kw * kw;
+    // Offline transformation, one kernel row (line of taps along x) at a time, or
+    // (paired-line bands) one instruction of r + 1 per input line pair.
+    const bool pair = p->band_h == 8;
+    const int nrows = pair ? radius + 1 : (ndim == 2 ? kw : kw * kw);
     p->nrows = nrows;
     std::vector<PackedRow> rows(nrows);
     std::vector<uint32_t> ipack(((nrows + 1) / 2) * 64, 0u);
@@ -321,11 +342,13 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     uint32_t mask = 0;
     for (int i = 0; i < nrows; ++i) {
       const double* row = p->coeffs.data() + (size_t)i * kw;
-      bool nz = false;
-      for (int t = 0; t < kw; ++t) nz |= row[t] != 0.0;
+      bool nz = pair;
+      for (int t = 0; t < kw && !pair; ++t) nz |= row[t] != 0.0;
       if (nz) mask |= 1u << i;
       std::string err;
-      if (!pack_row(row, radius, p->operand, std::min(p->split, 2), &rows[i], &err)) {
+      const bool ok = pair ? pack_pair(p->coeffs.data(), radius, p->operand, std::min(p->split, 2), i, &rows[i], &err)
+                           : pack_row(row, radius, p->operand, std::min(p->split, 2), &rows[i], &err);
+      if (!ok) {
         spider_plan_destroy(p);
         return fail(SPIDER_ERR_INVALID, "%s", err.c_str());
       }
@@ -348,13 +371,15 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       return hip_fail(e, "operand upload");
     }
     p->tile_h = o.tile_h ? o.tile_h : (ndim == 2 ? auto_tile_h_2d(p) : auto_tile_h_3d(p));
+    if (pair) p->tile_h = std::min(p->tile_h + (p->tile_h & 1), p->ny + (p->ny & 1));  // pairs start on even rows
     BandGrid& g = p->grid_template;
     std::memset(&g, 0, sizeof(g));
     g.nz = p->nz;
     g.ny = p->ny;
     g.nx = p->nx;
     g.seg_h = p->tile_h;
-    g.nstrips = ndim == 2 ? (p->nx + 8 + kStripW - 1) / kStripW : (p->nx + kStripW - 1) / kStripW;
+    g.nstrips = pair ? (p->nx + kPairWinLead + kStripWPair - 1) / kStripWPair
+                     : (ndim == 2 ? (p->nx + 8 + kStripW - 1) / kStripW : (p->nx + kStripW - 1) / kStripW);
     g.apack = static_cast<const uint4*>(p->d_apack);
     g.ipack = static_cast<const uint32_t*>(p->d_ipack);
     g.dpack = static_cast<const uint4*>(p->d_dpack);
@@ -372,7 +397,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     // amortised over more lines): at least 64 lines (2-D) or 16 planes (3-D).
     p->grid_batch = g;
     {
-      const int hb = ndim == 2 ? std::min(p->ny, std::max(p->tile_h, 64)) : std::min(p->nz, std::max(p->tile_h, 16));
+      int hb = ndim == 2 ? std::min(p->ny, std::max(p->tile_h, 64)) : std::min(p->nz, std::max(p->tile_h, 16));
+      if (pair) hb += hb & 1;
       p->grid_batch.seg_h = hb;
       if (ndim == 2)
         p->grid_batch.nsegs_y = (p->ny + hb - 1) / hb;
@@ -460,9 +486,10 @@ spider_status spider_plan_destroy(spider_plan_t p) {
 }
 
 spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* tile_h, int* nrows_nonzero,
-                               size_t* scratch_bytes, int* time_block, int* tile_h2) {
+                               size_t* scratch_bytes, int* time_block, int* tile_h2, int* band_height) {
   clear_err();
   if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
+  if (band_height) *band_height = p->engine == SPIDER_ENGINE_DIRECT ? 0 : p->band_h;
   if (engine) *engine = p->engine;
   if (carry) *carry = p->carry;
   if (tile_h) *tile_h = p->tile_h;
@@ -509,6 +536,26 @@ spider_status spider_pack_row(const double* row, int radius, int operand, int sp
   PackedRow pr;
   std::string err;
   if (!pack_row(row, radius, operand, split, &pr, &err)) return fail(SPIDER_ERR_INVALID, "%s", err.c_str());
+  std::memcpy(a_bits, pr.a, sizeof(pr.a));
+  std::memcpy(idx, pr.idx, sizeof(pr.idx));
+  if (dense_bits) std::memcpy(dense_bits, pr.dense, sizeof(pr.dense));
+  return SPIDER_OK;
+}
+
+spider_status spider_pair_gather_positions(int pos[16]) {
+  clear_err();
+  if (!pos) return fail(SPIDER_ERR_INVALID, "pos is NULL");
+  pair_gather_positions(pos);
+  return SPIDER_OK;
+}
+
+spider_status spider_pack_pair(const double* w, int radius, int operand, int split, int k, uint16_t* a_bits,
+                               uint16_t* idx, uint16_t* dense_bits) {
+  clear_err();
+  if (!w || !a_bits || !idx) return fail(SPIDER_ERR_INVALID, "NULL argument");
+  PackedRow pr;
+  std::string err;
+  if (!pack_pair(w, radius, operand, split, k, &pr, &err)) return fail(SPIDER_ERR_INVALID, "%s", err.c_str());
   std::memcpy(a_bits, pr.a, sizeof(pr.a));
   std::memcpy(idx, pr.idx, sizeof(pr.idx));
   if (dense_bits) std::memcpy(dense_bits, pr.dense, sizeof(pr.dense));

@@ -72,7 +72,7 @@ def test_f32_carry_rounded_equals_16bit_carry(operand, engine):
     x16, _ = to_dev(wl["make_grid"](), operand)
     x32 = x16.to(torch.float32)
     for tb in (1, 0):
-        p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, engine=engine, time_block=tb)
+        p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, engine=engine, time_block=tb, band_height=16)
         y16 = torch.empty_like(x16)
         p16.apply(x16, y16, 9)
         p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=2, operand=operand)

@@ -278,7 +278,11 @@ def test_full_size_box3d27p_sampled(oracle_mod):
 @pytest.mark.parametrize("carry", ["f16", "bf16"])
 @pytest.mark.parametrize("engine", ["sparse", "dense"])
 @pytest.mark.parametrize("shape", [(300, 520), (77, 301), (1, 1), (5, 8), (260, 1032), (41, 241), (129, 480)])
-def test_time_block_bitwise_equals_single_steps(carry, engine, shape):
+@pytest.mark.parametrize("band", [16, 8])
+def test_time_block_bitwise_equals_single_steps(carry, engine, shape, band):
+    # 16-point bands: two fused steps equal two single steps bit for bit for every r.
+    # Paired-line bands: bit for bit for even r (the intermediate line pairs then start
+    # on even rows, as the single step's output pairs do); for odd r within rounding.
     import torch
     rng = np.random.default_rng(shape[0] * 7 + shape[1])
     for kind, r in [("box", 1), ("box", 2), ("box", 3), ("star", 3)]:
@@ -287,13 +291,18 @@ def test_time_block_bitwise_equals_single_steps(carry, engine, shape):
         w[m] = rng.uniform(-1, 1, int(m.sum()))
         w /= np.abs(w).sum()
         xd, _ = to_dev(rng.uniform(-1, 1, shape), carry)
-        p1 = sp.Plan(w, shape, carry=carry, engine=engine, time_block=1)
-        p2 = sp.Plan(w, shape, carry=carry, engine=engine, time_block=2)
+        p1 = sp.Plan(w, shape, carry=carry, engine=engine, time_block=1, band_height=band)
+        p2 = sp.Plan(w, shape, carry=carry, engine=engine, time_block=2, band_height=band)
         for steps in (1, 2, 3, 4, 7):
             a, b = torch.empty_like(xd), torch.empty_like(xd)
             p1.apply(xd, a, steps)
             p2.apply(xd, b, steps)
-            assert torch.equal(a, b), (kind, r, steps)
+            if band == 16 or r % 2 == 0 or steps == 1:
+                assert torch.equal(a, b), (kind, r, steps)
+            else:
+                fa, fb = from_dev(a), from_dev(b)
+                tol = (2e-3 if carry == "f16" else 3e-2) * np.abs(fa).max() + 1e-7  # floor: values can underflow to 0
+                assert np.abs(fb - fa).max() <= tol, (kind, r, steps)
 
 
 def test_time_block_tile_heights_and_aliasing(oracle_mod):

@@ -209,6 +209,92 @@ def test_packed_band_product_matches_oracle(oracle_mod):
     assert np.array_equal(out, ref)
 
 
+# ------------------------------------------------------------------ paired-line band (L = 8)
+
+
+def test_pair_gather_positions_groups():
+    pos = sp.pair_gather_positions()
+    assert sorted(pos.tolist()) == list(range(16))
+    for q in range(4):
+        grp = pos[4 * q:4 * q + 4]
+        # each 2:4 group joins a 32-bit column pair with the pair 8 columns to its right
+        assert grp[1] == grp[0] + 1 and grp[3] == grp[2] + 1 and grp[2] == grp[0] + 8 and grp[0] % 2 == 0
+
+
+def _pair_expected(w, r, k, hi_fn, lo_fn):
+    pos = sp.pair_gather_positions()
+    kw = 2 * r + 1
+    A = np.zeros((16, 64))
+    for phi in range(2):
+        for m in range(8):
+            for lam in range(2):
+                row = 2 * k + lam - phi
+                if not 0 <= row < kw:
+                    continue
+                for rho, part in enumerate((hi_fn(w[row]), lo_fn(w[row]))):
+                    for s_ in range(16):
+                        t = pos[s_] - 4 - m + r
+                        if 0 <= t < kw:
+                            A[8 * phi + m, 32 * lam + 16 * rho + s_] = part[t]
+    return A
+
+
+@pytest.mark.parametrize("split", [1, 2])
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_pack_pair_decodes_to_definition(r, split):
+    rng = np.random.default_rng(40 + r)
+    w = rng.uniform(-1, 1, (2 * r + 1, 2 * r + 1))
+
+    def hi(v):
+        return v.astype(np.float16).astype(np.float64)
+
+    def lo(v):
+        return (v - hi(v)).astype(np.float16).astype(np.float64) if split == 2 else np.zeros_like(v)
+
+    for k in range(r + 1):
+        a, idx, dense = sp.pack_pair(w, r, k, "f16", split)
+        A = _decode_smfmac_A(a, idx, np.float16)
+        E = _pair_expected(w, r, k, hi, lo)
+        assert np.array_equal(A, E), k
+        D = dense.view(np.float16).astype(np.float64)
+        for lane in range(64):
+            m, k0 = lane % 16, 8 * (lane // 16)
+            assert np.array_equal(D[lane, :8], E[m, k0:k0 + 8])
+            assert np.array_equal(D[lane, 8:], E[m, 32 + k0:32 + k0 + 8])
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_pair_band_product_matches_oracle(oracle_mod, r):
+    # The whole 2-D step through the packed paired operands (CPU emulation of the
+    # 16x16x64 products, B = the two windows of an input pair, each twice for hi/lo)
+    # equals the oracle bit for bit on integer data.
+    rng = np.random.default_rng(70 + r)
+    w = rng.integers(-3, 4, (2 * r + 1, 2 * r + 1)).astype(np.float64)
+    ny, nx = 14, 128
+    x = rng.integers(-5, 6, (ny, nx)).astype(np.float64)
+    As = [_decode_smfmac_A(*sp.pack_pair(w, r, k, "f16", 2)[:2], np.float16) for k in range(r + 1)]
+    pos = sp.pair_gather_positions()
+    xp = np.zeros((ny + 2 * r + 4, nx + 8))
+    xp[r + 2:r + 2 + ny, 4:4 + nx] = x           # grid row y at r + 2 + y, column x at 4 + x
+    out = np.zeros((ny + 1, nx))
+    for i in range(0, ny, 2):                    # output pair (i, i + 1)
+        acc = np.zeros((16, 16))
+        for k in range(r + 1):
+            j = i - r + 2 * k                    # input pair (j, j + 1)
+            B = np.zeros((64, 16))
+            for n in range(16):
+                for lam in range(2):
+                    win = xp[r + 2 + j + lam, 8 * n:8 * n + 16]    # columns 8n - 4 .. 8n + 11
+                    B[32 * lam:32 * lam + 16, n] = win[pos]
+                    B[32 * lam + 16:32 * lam + 32, n] = win[pos]
+            acc += As[k] @ B
+        for phi in range(2):
+            for n in range(16):
+                out[i + phi, 8 * n:8 * n + 8] = acc[8 * phi:8 * phi + 8, n]
+    ref = oracle_mod.apply(w, x, 1)
+    assert np.array_equal(out[:ny], ref)
+
+
 # ------------------------------------------------------------------ rounding
 
 
@@ -282,6 +368,13 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
     o = opts(carry=1, engine=2, operand=1)  # operands are 16-bit
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    o = opts(band_height=12)
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    o = opts(band_height=8)  # paired-line bands: radius <= 3
+    w4 = np.ones((9, 9)) / 81
+    assert L.spider_plan(w4.ctypes.data, 2, shp, 4, ctypes.byref(o), ctypes.byref(h)) == 2
+    o = opts(band_height=8, carry=1, engine=1)  # and a 16-bit carry
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2
     assert L.spider_apply(None, None, None, 1, None) == 1
     assert L.spider_plan_destroy(None) == 0
     with pytest.raises(sp.SpiderError):
