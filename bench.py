@@ -33,7 +33,7 @@ TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": 
 KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band_pair.hip", "paper_2506_22035_amd/csrc/band_pair.h",
                   "paper_2506_22035_amd/csrc/band_common.h"]
 # the dominant kernel of the headline run: two fused time steps per launch
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_tb2_box49p_f16_10240_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_pair_tb2_box49p_f16_10240_traffic.json")
 
 
 def kernel_source_hash():
@@ -141,6 +141,28 @@ def serving(torch, sp, si, n, fractions, seed=11):
     return out
 
 
+def size_trend(torch, sp, si, args):
+    """Throughput versus grid size for the Box-2D49P stencil (the paper's size trend, Fig. 11):
+    square grids of the headline recipe's stencil and field, 50 steps per pass, fp16 carry."""
+    wl = si.workload("box2d49p_10240")
+    res = []
+    for n in (512, 1024, 2048, 4096, 6144, 8192, 10240, 12288, 14336):
+        x = torch.from_numpy(si.grid_sinusoids((n, n), wl["seeds"]["grid"])).to(torch.float16).to("cuda:0")
+        y = torch.empty_like(x)
+        row = {"n": n, "grid_MB": round(2 * n * n / 1e6, 1)}
+        for band in (8, 16):
+            p = sp.Plan(wl["coeffs"], (n, n), carry="f16", autotune=True, band_height=band)
+            p.apply(x, y, 50)
+            k = max(3, min(50, int(4e9 / (n * n * 50))))
+            ms, _ = timed_applies(torch, p, x, y, 50, k, torch.cuda.current_stream())
+            row["band%d_GStencil_s" % band] = round(n * n * 50 * k / (ms * 1e-3) / 1e9, 1)
+            p.close()
+        res.append(row)
+        del x, y
+    return {"metric": "GStencil/s versus grid size (Box-2D49P, 50 steps, fp16 carry, sparse engine)",
+            "config": {"workload": "box2d49p_size_trend", "steps_per_pass": 50}, "trend": res}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +189,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="run only the serving-mix sweep (1000 requests per rate) and print its JSON line")
     ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--trend", action="store_true",
+                    help="run only the 2-D size trend (Box-2D49P recipe, square grids 512^2 .. 14336^2) and print "
+                         "its JSON line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -178,6 +203,10 @@ def main():
 
     import paper_2506_22035_amd as sp
     import stencil_inputs as si
+
+    if args.trend:
+        print(json.dumps(size_trend(torch, sp, si, args)))
+        return
 
     if args.serving:
         res = serving(torch, sp, si, args.serving_requests, [0.25, 0.5, 1.0, 1.5])
