@@ -266,9 +266,11 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ("direct%dd_kernel" if args.engine == "direct" else
-                       ("band%dd_f32_kernel" if args.carry == "f32" else
-                        ("band%dd_pair" if info["band_height"] == 8 else "band%dd")
-                        + ("_tb2_kernel" if tb == 2 else "_kernel"))) % len(shape)
+                       ("band%dd_pair_f32_kernel<fused>" if (args.carry == "f32" and tb == 2) else
+                        ("band%dd_pair_f32_kernel" if (args.carry == "f32" and info["band_height"] == 8) else
+                         ("band%dd_f32_kernel" if args.carry == "f32" else
+                          ("band%dd_pair" if info["band_height"] == 8 else "band%dd")
+                          + ("_tb2_kernel" if tb == 2 else "_kernel"))))) % len(shape)
                       + "<r=%d,%s,%s>" % ((wl["coeffs"].shape[0] - 1) // 2, args.carry, args.engine),
             "time_steps_per_launch": steps_per_launch,
             "alg_bytes_per_launch": alg_bytes,
@@ -291,7 +293,8 @@ def main():
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": args.carry, "data": "synthetic",
            "config": {"workload": args.workload, "grid": list(shape),
-                      "time_steps_per_step": T, "carry": args.carry, "operand": args.carry,
+                      "time_steps_per_step": T, "carry": args.carry,
+                      "operand": "f16" if (args.carry == "f32" and args.engine != "direct") else args.carry,
                       "accumulate": "f32" if args.carry in ("f16", "bf16") else args.carry,
                       "engine": info["engine"], "split": args.split if args.engine != "direct" else None,
                       "tile_h": info["tile_h"],

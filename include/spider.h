@@ -75,7 +75,8 @@ typedef struct {
                       plan time and keep the fastest (results cached per shape, radius,
                       engine and dtype for the life of the process); 0 = occupancy heuristic */
     int time_block; /* time steps fused per launch: 0 = automatic (two for 2-D grids of
-                       radius <= 3 on the matrix engines with a 16-bit carry, else one),
+                       radius <= 3 on the matrix engines with a 16-bit carry or with
+                       paired-line bands, else one),
                        1 = one step per launch, 2 = two where supported.  Results are
                        identical bit for bit. */
     int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16
@@ -84,8 +85,8 @@ typedef struct {
     int band_height; /* output points per band row on the matrix engines: 0 = automatic
                         (8 where it applies, else 16), 16 = 16-point chunks with 32-column
                         windows (any radius), 8 = the paper's band height L = 2r + 2 <= 8
-                        with two output lines per instruction (2-D, radius <= 3, 16-bit
-                        carry; segment heights are rounded up to even numbers).  The two
+                        with two output lines per instruction (2-D, radius <= 3, 16-bit or
+                        fp32 carry; segment heights are rounded up to even numbers).  The two
                         give different rounding orders.  With band height 8 and odd r, two
                         fused steps (time_block 2) round differently from two single
                         steps; with band height 16 they are identical bit for bit. */

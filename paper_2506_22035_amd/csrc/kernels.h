@@ -61,6 +61,12 @@ int band2d_pair_blocks_per_cu(int r, int operand, int engine);
 constexpr int kStripWPair2 = 240;
 hipError_t launch_band2d_pair_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
 int band2d_pair_tb2_blocks_per_cu(int r, int operand, int engine);
+// Paired-line bands on fp32 grids: 16-bit operands split from the fp32 values
+// (x_hi, and x_lo when `xlo`); one step (256-column strips) or two fused steps
+// (`fused`, 240 stored columns per strip).
+hipError_t launch_band2d_pair_f32(int r, int operand, int engine, bool xlo, bool fused, const BandGrid& g,
+                                  hipStream_t s);
+int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, bool fused);
 
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);

@@ -60,7 +60,9 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = p->band_h == 8            ? band2d_pair_blocks_per_cu(p->r, p->operand, p->engine)
+  int per_cu = p->band_h == 8 && p->carry == SPIDER_F32
+                   ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, false)
+               : p->band_h == 8        ? band2d_pair_blocks_per_cu(p->r, p->operand, p->engine)
                : p->carry == SPIDER_F32 ? band2d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3)
                                         : band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
   if (per_cu <= 0) per_cu = 8;
@@ -121,7 +123,8 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
     BandGrid g = p->grid_template;
     g.in = src;
     g.out = dst;
-    e = launch_band2d_pair(p->r, p->operand, p->engine, g, s);
+    e = p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, false, g, s)
+                               : launch_band2d_pair(p->r, p->operand, p->engine, g, s);
   } else if (p->ndim == 2 && p->carry == SPIDER_F32) {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -146,8 +149,9 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   BandGrid g = p->grid_tb2;
   g.in = src;
   g.out = dst;
-  hipError_t e = p->band_h == 8 ? launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s)
-                                : launch_band2d_tb2(p->r, p->operand, p->engine, g, s);
+  hipError_t e = p->band_h != 8               ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
+                 : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, true, g, s)
+                                          : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SPIDER_OK;
 }
@@ -168,8 +172,9 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = p->band_h == 8 ? band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine)
-                              : band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine);
+  int per_cu = p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
+               : p->carry == SPIDER_F32 ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, true)
+                                        : band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
   const long long nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;  // 240 columns in both layouts
@@ -278,9 +283,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   if (o.time_block < 0 || o.time_block > 2) return fail(SPIDER_ERR_INVALID, "time_block must be 0, 1 or 2");
   if (o.band_height != 0 && o.band_height != 8 && o.band_height != 16)
     return fail(SPIDER_ERR_INVALID, "band_height must be 0, 8 or 16");
-  if (o.band_height == 8 && !(matrix && ndim == 2 && radius <= 3 && low && shape[1] < (1LL << 28)))
-    return fail(SPIDER_ERR_UNSUPPORTED,
-                "band_height 8 (paired-line bands) needs a matrix engine, a 2-D grid, radius <= 3 and a 16-bit carry");
+  if (o.band_height == 8 && !(matrix && ndim == 2 && radius <= 3 && shape[1] < (1LL << 28)))
+    return fail(SPIDER_ERR_UNSUPPORTED, "band_height 8 (paired-line bands) needs a matrix engine, a 2-D grid and radius <= 3");
 
   auto* p = new spider_plan_s();
   p->ndim = ndim;
@@ -294,7 +298,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   p->split = o.split;
   p->use_graph = o.use_graph;
   // paired-line bands by default where they apply (fewer instructions per output)
-  const bool pair_ok = matrix && ndim == 2 && radius <= 3 && low && shape[1] < (1LL << 28);
+  const bool pair_ok = matrix && ndim == 2 && radius <= 3 && shape[1] < (1LL << 28);
   p->band_h = (o.band_height == 8 || (o.band_height == 0 && pair_ok)) ? 8 : 16;
   const int kw = 2 * radius + 1;
   const int ncoef = ndim == 2 ? kw * kw : kw * kw * kw;
@@ -407,7 +411,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       p->grid_batch.nblocks = p->grid_batch.nstrips * p->grid_batch.nsegs_y * p->grid_batch.nsegs_z;
     }
     // two fused steps per launch: 2-D, radius <= 3, 16-bit carry
-    const bool tb2_ok = ndim == 2 && radius <= 3 && low;
+    const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair);
     p->time_block = (o.time_block != 1 && tb2_ok) ? 2 : 1;
     if (p->time_block == 2) {
       p->grid_tb2 = g;

@@ -29,10 +29,11 @@ def run(plan, x_dev, steps):
     return from_dev(y)
 
 
+@pytest.mark.parametrize("band", [8, 16])
 @pytest.mark.parametrize("operand", ["f16", "bf16"])
 @pytest.mark.parametrize("engine", ["sparse", "dense"])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_integer_exact_input_split(oracle_mod, operand, engine, shape):
+def test_integer_exact_input_split(oracle_mod, operand, engine, shape, band):
     # All-ones 3x3 taps on inputs in {1, 2}: the inputs of the fifth step reach ~1e4,
     # beyond the 16-bit significand but exact as x_hi + x_lo, and the outputs (~1e5)
     # are exact in fp32.  The other cases mix signs.
@@ -43,7 +44,7 @@ def test_integer_exact_input_split(oracle_mod, operand, engine, shape):
         r = (w.shape[0] - 1) // 2
         x = si.grid_integer(shape, lo, hi, 60 + shape[1])
         xd, x64 = to_dev(x, "f32")
-        plan = sp.Plan(w, shape, carry="f32", engine=engine, split=3, operand=operand)
+        plan = sp.Plan(w, shape, carry="f32", engine=engine, split=3, operand=operand, band_height=band)
         got = run(plan, xd, steps)
         ref = oracle_mod.apply(w, x64, steps)
         assert np.abs(oracle_mod.apply(w, x64, steps - 1)).max() < 65504
@@ -64,34 +65,39 @@ def test_without_input_split_large_values_are_rounded(oracle_mod, operand):
     assert not np.array_equal(got2, ref)
 
 
+@pytest.mark.parametrize("band", [16, 8])
 @pytest.mark.parametrize("operand", ["f16", "bf16"])
 @pytest.mark.parametrize("engine", ["sparse", "dense"])
-def test_f32_carry_rounded_equals_16bit_carry(operand, engine):
+def test_f32_carry_rounded_equals_16bit_carry(operand, engine, band):
     import torch
     wl = si.workload("box2d49p_10240", small=True)
     x16, _ = to_dev(wl["make_grid"](), operand)
     x32 = x16.to(torch.float32)
-    for tb in (1, 0):
-        p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, engine=engine, time_block=tb, band_height=16)
+    for tb in (1, 2):
+        p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, engine=engine, time_block=tb, band_height=band)
         y16 = torch.empty_like(x16)
         p16.apply(x16, y16, 9)
-        p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=2, operand=operand)
+        # the fp32 16-point kernel runs one step per launch; paired bands fuse like the 16-bit plan
+        p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=2, operand=operand,
+                      band_height=band, time_block=tb if band == 8 else 1)
         y32 = torch.empty_like(x32)
         p32.apply(x32, y32, 9)
         torch.cuda.synchronize()
         assert torch.equal(y32.to(x16.dtype), y16), tb
 
 
+@pytest.mark.parametrize("band", [8, 16])
 @pytest.mark.parametrize("operand", ["f16", "bf16"])
 @pytest.mark.parametrize("engine", ["sparse", "dense"])
 @pytest.mark.parametrize("name", ["box2d49p_10240", "star2d13p_8192"])
-def test_workload_tolerance_input_split(oracle_mod, operand, engine, name):
+def test_workload_tolerance_input_split(oracle_mod, operand, engine, name, band):
     wl = si.workload(name, small=True)
     xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
-    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=3, operand=operand)
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=3, operand=operand,
+                   band_height=band)
     got = run(plan, xd, wl["steps"])
     rms, mx = rel_errors(got, oracle_mod.apply(wl["coeffs"], x64, wl["steps"]))
-    print("%s f32 carry, %s operands, %s: rel-RMS %.3e rel-max %.3e" % (name, operand, engine, rms, mx))
+    print("%s f32 carry, %s operands, %s, band %d: rel-RMS %.3e rel-max %.3e" % (name, operand, engine, band, rms, mx))
     tr, tm = TOL3[operand]
     assert rms <= tr and mx <= tm
 

@@ -373,7 +373,7 @@ def test_invalid_arguments_rejected_without_gpu():
     o = opts(band_height=8)  # paired-line bands: radius <= 3
     w4 = np.ones((9, 9)) / 81
     assert L.spider_plan(w4.ctypes.data, 2, shp, 4, ctypes.byref(o), ctypes.byref(h)) == 2
-    o = opts(band_height=8, carry=1, engine=1)  # and a 16-bit carry
+    o = opts(band_height=8, carry=1, engine=3)  # and a matrix engine
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2
     assert L.spider_apply(None, None, None, 1, None) == 1
     assert L.spider_plan_destroy(None) == 0
