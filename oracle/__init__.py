@@ -52,7 +52,7 @@ def apply(coeffs, x, steps, nthreads=0):
     """Return S^steps(x) in fp64.
 
     coeffs: (2r+1,)*ndim array, w[dz][dy][dx] multiplies x[p + (dz, dy, dx) - r].
-    x: 2-D or 3-D array (any real dtype; converted exactly to fp64).
+    x: 1-D, 2-D or 3-D array (any real dtype; converted exactly to fp64).
     """
     w = np.ascontiguousarray(coeffs, dtype=np.float64)
     xin = np.ascontiguousarray(x, dtype=np.float64)

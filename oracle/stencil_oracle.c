@@ -1,5 +1,5 @@
 /*
- * FP64 CPU oracle for iterated 2-D / 3-D stencils with a fixed zero halo.
+ * FP64 CPU oracle for iterated 1-D / 2-D / 3-D stencils with a fixed zero halo.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
  * calls this file; only the tests, the smoke check and the CPU-baseline leg of
@@ -22,12 +22,12 @@
  * rounded to fp64 and added to an fp64 accumulator in that order (the file is
  * compiled with -ffp-contract=off so no fused multiply-add changes a rounding).
  * The coefficient array is correlation-ordered: w[o] multiplies x[p + o]; no
- * flip.  Layout: row-major, x fastest: 2-D x[y][x], 3-D x[z][y][x];
+ * flip.  Layout: row-major, x fastest: 1-D x[x], 2-D x[y][x], 3-D x[z][y][x];
  * coefficients w[dz][dy][dx] with each index running 0..2r (offset + r).
  *
- * Parallelism: OpenMP over the outermost grid axis only (each output point is
- * still computed by one thread in the order above, so results do not depend on
- * the thread count).
+ * Parallelism: OpenMP over the outermost grid axis only (1-D: over points;
+ * each output point is still computed by one thread in the order above, so
+ * results do not depend on the thread count).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -35,6 +35,22 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* One step in 1-D (the paper's d = 1 case, Sec. 2.2). */
+static void step1d(int64_t nx, int r, const double* w, const double* x, double* y) {
+#pragma omp parallel for schedule(static)
+    for (int64_t ix = 0; ix < nx; ++ix) {
+        double acc = 0.0;
+        for (int64_t dx = -r; dx <= r; ++dx) {
+            const double c = w[dx + r];
+            if (c == 0.0) continue;
+            const int64_t sx = ix + dx;
+            const double v = (sx >= 0 && sx < nx) ? x[sx] : 0.0;
+            acc += c * v;
+        }
+        y[ix] = acc;
+    }
+}
 
 /* One step in 2-D.  Returns nothing; all sizes are validated by the caller. */
 static void step2d(int64_t ny, int64_t nx, int r, const double* w, const double* x, double* y) {
@@ -85,8 +101,8 @@ static void step3d(int64_t nz, int64_t ny, int64_t nx, int r, const double* w, c
 
 /*
  * oracle_stencil: apply `steps` Jacobi steps.
- *   ndim    2 or 3
- *   shape   ndim extents, slowest first ([ny, nx] or [nz, ny, nx]), each >= 1
+ *   ndim    1, 2 or 3
+ *   shape   ndim extents, slowest first ([nx], [ny, nx] or [nz, ny, nx]), each >= 1
  *   radius  r >= 0
  *   coeffs  (2r+1)^ndim fp64 coefficients, layout described above
  *   in      input grid (not modified unless in == out)
@@ -97,7 +113,7 @@ static void step3d(int64_t nz, int64_t ny, int64_t nx, int r, const double* w, c
  */
 int oracle_stencil(int ndim, const int64_t* shape, int radius, const double* coeffs,
                    const double* in, double* out, int steps, int nthreads) {
-    if ((ndim != 2 && ndim != 3) || !shape || radius < 0 || !coeffs || !in || !out || steps < 0) return -1;
+    if (ndim < 1 || ndim > 3 || !shape || radius < 0 || !coeffs || !in || !out || steps < 0) return -1;
     int64_t n = 1;
     for (int i = 0; i < ndim; ++i) {
         if (shape[i] < 1) return -1;
@@ -113,7 +129,8 @@ int oracle_stencil(int ndim, const int64_t* shape, int radius, const double* coe
     if (!a || !b) { free(a); free(b); return -2; }
     memcpy(a, in, (size_t)n * sizeof(double));
     for (int s = 0; s < steps; ++s) {
-        if (ndim == 2) step2d(shape[0], shape[1], radius, coeffs, a, b);
+        if (ndim == 1) step1d(shape[0], radius, coeffs, a, b);
+        else if (ndim == 2) step2d(shape[0], shape[1], radius, coeffs, a, b);
         else step3d(shape[0], shape[1], shape[2], radius, coeffs, a, b);
         double* t = a; a = b; b = t;
     }

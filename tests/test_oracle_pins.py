@@ -179,3 +179,71 @@ def test_sampled_point_matches_full_grid(oracle_mod):
         x0, x1 = max(0, px - T * r), min(70, px + T * r + 1)
         sub = oracle_mod.apply(w, x[y0:y1, x0:x1], T)
         assert sub[py - y0, px - x0] == full[py, px]
+
+
+# ------------------------------------------------------------------ 1-D (the paper's d = 1 stencils)
+
+
+@pytest.mark.parametrize("r,n,steps", [(1, 37, 4), (2, 64, 3), (3, 5, 2), (1, 1, 3), (2, 1000, 6)])
+def test_1d_matches_scipy_correlate(oracle_mod, r, n, steps):
+    rng = np.random.default_rng(30 + r)
+    w = rng.uniform(-1, 1, 2 * r + 1)   # asymmetric: a flip fails
+    x = rng.uniform(-1, 1, n)
+    got = oracle_mod.apply(w, x, steps)
+    ref = _scipy_steps(w, x, steps)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_1d_delta_response_is_unflipped(oracle_mod):
+    w = np.array([0.5, -1.25, 2.0, 0.75, -3.0])
+    x = np.zeros(15)
+    x[7] = 1.0
+    y = oracle_mod.apply(w, x, 1)
+    for o in range(-2, 3):
+        assert y[7 - o] == w[o + 2]
+    assert np.count_nonzero(y) == 5
+
+
+@pytest.mark.parametrize("n", [1, 7, 20])
+def test_1d_binomial_closed_form(oracle_mod, n):
+    x = np.zeros(2 * n + 31)
+    c = n + 15
+    x[c] = 1.0
+    y = oracle_mod.apply(np.array([0.25, 0.5, 0.25]), x, n)
+    expect = np.zeros_like(x)
+    for k in range(2 * n + 1):
+        expect[c - n + k] = math.comb(2 * n, k) / 4.0 ** n
+    assert np.array_equal(y, expect)
+
+
+@pytest.mark.parametrize("m,steps", [(1, 9), (4, 5), (11, 3)])
+def test_1d_heat_zero_halo_eigenvector(oracle_mod, m, steps):
+    # u_j = sin(pi m (j + 1) / (N + 1)) is an eigenvector of [a, 1 - 2a, a] with the zero
+    # halo, eigenvalue 1 - 2a (1 - cos(pi m / (N + 1))).
+    a, N = 0.2, 23
+    u = np.sin(np.pi * m * (np.arange(N) + 1) / (N + 1))
+    lam = 1.0 - 2.0 * a * (1.0 - np.cos(np.pi * m / (N + 1)))
+    y = oracle_mod.apply(np.array([a, 1 - 2 * a, a]), u, steps)
+    assert np.max(np.abs(y - lam ** steps * u)) <= 1e-14
+
+
+def test_1d_equals_2d_single_row(oracle_mod):
+    # a 1-D stencil on a line is the 2-D stencil with only the centre kernel row on a 1 x n grid
+    rng = np.random.default_rng(44)
+    w1 = rng.uniform(-1, 1, 5)
+    w2 = np.zeros((5, 5))
+    w2[2] = w1
+    x = rng.uniform(-1, 1, 301)
+    assert np.array_equal(oracle_mod.apply(w1, x, 4), oracle_mod.apply(w2, x[None, :], 4)[0])
+
+
+def test_1d_linearity_and_constant_interior(oracle_mod):
+    rng = np.random.default_rng(45)
+    w = rng.uniform(0, 1, 5)
+    w /= w.sum()
+    a, b = rng.uniform(-1, 1, 200), rng.uniform(-1, 1, 200)
+    lhs = oracle_mod.apply(w, 2.5 * a - 0.75 * b, 3)
+    rhs = 2.5 * oracle_mod.apply(w, a, 3) - 0.75 * oracle_mod.apply(w, b, 3)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-14
+    y = oracle_mod.apply(w, np.full(200, 3.0), 5)
+    assert np.max(np.abs(y[10:-10] - 3.0)) <= 1e-14
