@@ -169,7 +169,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20, help="timed passes (each = 50 time steps)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="box2d49p_10240",
-                    choices=["box2d49p_10240", "star2d13p_8192", "box2d9p_256_f64", "box3d27p_512", "heat3d_256"],
+                    choices=["box2d49p_10240", "star2d13p_8192", "box2d9p_256_f64", "box3d27p_512", "heat3d_256",
+                             "1d3p_10240000", "1d5p_10240000"],
                     help="workload recipe (default: the headline Box-2D49P)")
     ap.add_argument("--carry", default=None, choices=["f16", "bf16", "f32", "f64"],
                     help="grid dtype (default f16; f64 for box2d9p_256_f64)")
@@ -226,7 +227,7 @@ def main():
     headline = args.workload == "box2d49p_10240" and args.carry in ("f16", "bf16")
     T = wl["steps"]
     shape = tuple(wl["shape"])
-    ny, nx = shape[-2], shape[-1]
+    ny, nx = (shape[-2] if len(shape) > 1 else 1), shape[-1]
     npts = int(np.prod(shape))
     x32 = wl["make_grid"](np.float64 if args.carry == "f64" else np.float32)
     tdt = sp.torch_dtype(args.carry)

@@ -1,7 +1,7 @@
 /*
  * spider.h -- C ABI of the MI355X (gfx950) strided-swap stencil library.
  *
- * The library applies iterated 2-D / 3-D stencils (SPIDER, Sec. 2.2: each
+ * The library applies iterated 1-D / 2-D / 3-D stencils (SPIDER, Sec. 2.2: each
  * point becomes a weighted linear combination of its radius-r neighbourhood,
  * repeated over time steps, each step reading only the previous one) by
  * lowering every kernel row to a banded matrix product Y = K X (Sec. 3.1.1),
@@ -18,7 +18,7 @@
  *  - Every function returns a spider_status and never throws.  On failure a
  *    human-readable message is available from spider_last_error() (per thread).
  *  - Grids are interior-only, contiguous, row-major with x fastest:
- *    2-D grid[y][x], 3-D grid[z][y][x]; `shape` lists extents slowest first.
+ *    1-D grid[x], 2-D grid[y][x], 3-D grid[z][y][x]; `shape` lists extents slowest first.
  *    The halo is a fixed zero (Dirichlet-0) boundary of width r on every side.
  *  - Coefficients are fp64, (2r+1)^ndim of them, laid out w[dz][dy][dx] with
  *    each index 0..2r; w[o] multiplies x[p + o - r] (correlation, no flip).
@@ -102,8 +102,10 @@ spider_status spider_opts_default(spider_opts* o);
  * spider_plan: offline transformation (Sec. 3.1, done once per stencil; the paper
  * reports it as a small rule-based cost outside the timed loop, Sec. 4.2).
  *   coeffs  host fp64 array, (2r+1)^ndim, layout above; copied, not retained
- *   ndim    2 or 3
- *   shape   host array of ndim extents, each in [1, 2^31)
+ *   ndim    1, 2 or 3 (1-D lines run on the 16-point band engine, one step per launch,
+ *           or on the direct engine)
+ *   shape   host array of ndim extents, each in [1, 2^31); a line (the last extent)
+ *           may hold at most 2^30 - 1 bytes of state
  *   radius  1..7 (r = 7 is the largest radius the paper works through, Sec. 3.2)
  *   opts    NULL for defaults
  *   out     receives the plan handle

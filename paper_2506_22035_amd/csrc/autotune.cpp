@@ -37,6 +37,12 @@ void set_tile(spider_plan_s* p, int h) {
   BandGrid& g = p->grid_template;
   g.seg_h = h;
   if (p->engine != SPIDER_ENGINE_DIRECT) {
+    if (p->ndim == 1) {
+      g.nsegs_y = (g.nstrips + h - 1) / h;
+      g.nsegs_z = 1;
+      g.nblocks = g.nsegs_y;
+      return;
+    }
     if (p->ndim == 2) {
       g.nsegs_y = (p->ny + h - 1) / h;
       g.nsegs_z = 1;
@@ -69,7 +75,7 @@ spider_status autotune_tile(spider_plan_s* p) {
       return SPIDER_OK;
     }
   }
-  const int n = p->ndim == 3 ? p->nz : p->ny;
+  const int n = p->ndim == 3 ? p->nz : (p->ndim == 2 ? p->ny : p->grid_template.nstrips);
   const std::vector<int> cand = candidates(p->tile_h, n);
   void* tmp = nullptr;
   hipError_t e = hipMalloc(&tmp, p->grid_bytes);

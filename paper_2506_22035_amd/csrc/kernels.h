@@ -68,6 +68,11 @@ hipError_t launch_band2d_pair_f32(int r, int operand, int engine, bool xlo, bool
                                   hipStream_t s);
 int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, bool fused);
 
+// 1-D band engine: the line is cut into nstrips = ceil((nx + 8) / 256) blocks of 256
+// outputs at x0 = 256 j - 8; each wave streams seg_h consecutive blocks (nblocks =
+// ceil(nstrips / seg_h)).  One packed kernel row.
+hipError_t launch_band1d(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
+
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
 int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);

@@ -143,6 +143,110 @@ void band2d_kernel(BandGrid g) {
   band2d_body<R, OP, ENG, ALIGNED>(g, w, lds);
 }
 
+// ----------------------------------------------------------------------------- 1-D
+// A 1-D line is cut into 256-point blocks at x0 = 256 j - 8 (the same chunk
+// alignment as the 2-D kernels); block j reads the window [x0 - 8, x0 + 264)
+// of the same array, so its halo is the neighbouring values, zero only beyond
+// the two ends.  One wave streams `seg_h` consecutive blocks, staging U blocks
+// ahead, and applies the single kernel row with one instruction per block.
+template <int R, int OP, int ENG, bool ALIGNED>
+__device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int U = 8;
+  const int lane = threadIdx.x;
+  const int nblk_total = g.nstrips;
+  const int b0 = w * g.seg_h;
+  const int nb = min(g.seg_h, nblk_total - b0);
+  const int nx = g.nx;
+  const u32x4 A0 = (ENG == 1) ? reinterpret_cast<const u32x4*>(g.apack)[lane] : (u32x4){0, 0, 0, 0};
+  const u32x4 Dh = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 0];
+  const u32x4 Dl = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 1];
+  const uint32_t I0 = (ENG == 1) ? g.ipack[lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const __amdgpu_buffer_rsrc_t rin =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * 2, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * 2, kRsrcWord3);
+  // lane c < 34 loads x in [x0 - 8 + 8c, x0 + 8c); blocks advance by 512 bytes
+  const int lx = lane < kRowChunks ? -16 + 8 * lane : 0x3ffffff0;
+  const int ox = -8 + 16 * (lane & 15) + 4 * (lane >> 4);
+  const int lw = chunk_lds_offset(lane, U * kLdsRowDw);
+  const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
+  auto load_blk = [&](int j) {  // block b0 + j, zero beyond the segment
+    const int x = 256 * (b0 + j) + lx;
+    const uint32_t off = (j < nb && lane < kRowChunks) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    return load_chunk<ALIGNED>(rin, off);
+  };
+  u32x4 stg[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) stg[q] = load_blk(q);
+  uint2 done[U];
+  const int nbody = (nb + U - 1) / U;
+  for (int jb = 0; jb < nbody * U; jb += U) {
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    if (jb > 0) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int j = jb - U + q;
+        const int x = 256 * (b0 + j) + ox;
+        const uint32_t off = (j < nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+        store_packed<ALIGNED>(rout, off, done[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) stg[q] = load_blk(jb + U + q);
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const uint32_t* lrow = lds + q * kLdsRowDw;
+      const u32x4 b = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+      const f32x4 acc = band_mma<OP, ENG, 0>((f32x4){0.f, 0.f, 0.f, 0.f}, A0, Dh, Dl, I0, b);
+      done[q] = pack_out<OP>(acc);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int j = nbody * U - U + q;
+    const int x = 256 * (b0 + j) + ox;
+    const uint32_t off = (j < nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    store_packed<ALIGNED>(rout, off, done[q]);
+  }
+}
+
+template <int R, int OP, int ENG, bool ALIGNED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void band1d_kernel(BandGrid g) {
+  __shared__ uint32_t lds[8 * kLdsRowDw + kLdsSpareDw];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band1d_body<R, OP, ENG, ALIGNED>(g, w, lds);
+}
+
+template <int OP, int ENG, bool AL>
+static hipError_t dispatch1d(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  switch (r) {
+    case 1: hipLaunchKernelGGL((band1d_kernel<1, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band1d_kernel<2, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band1d_kernel<3, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 4: hipLaunchKernelGGL((band1d_kernel<4, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 5: hipLaunchKernelGGL((band1d_kernel<5, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 6: hipLaunchKernelGGL((band1d_kernel<6, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 7: hipLaunchKernelGGL((band1d_kernel<7, OP, ENG, AL>), grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_band1d(int r, int operand, int engine, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2 && engine == 1) return al ? dispatch1d<2, 1, true>(r, g, s) : dispatch1d<2, 1, false>(r, g, s);
+  if (operand == 2 && engine == 2) return al ? dispatch1d<2, 2, true>(r, g, s) : dispatch1d<2, 2, false>(r, g, s);
+  if (operand == 3 && engine == 1) return al ? dispatch1d<3, 1, true>(r, g, s) : dispatch1d<3, 1, false>(r, g, s);
+  if (operand == 3 && engine == 2) return al ? dispatch1d<3, 2, true>(r, g, s) : dispatch1d<3, 2, false>(r, g, s);
+  return hipErrorInvalidValue;
+}
+
 // ----------------------------------------------------------------------------- 2-D, two fused steps
 // Temporal blocking (two time steps per launch).  The wave's first pass is the
 // single-step pass on 16 chunks starting 8 columns left of the stored strip

@@ -303,6 +303,39 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void di
 
 // ------------------------------------------------------------------ dispatch
 
+// 1-D: each lane computes 4 consecutive points; the 4 + 2R inputs it needs are
+// range-checked buffer loads (zero outside the line), taps applied in order.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void direct1d_kernel(const T* __restrict__ in, T* __restrict__ out, int nx,
+                                                       const T* __restrict__ w) {
+  const int x0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (x0 >= nx) return;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(in), (short)0, nx * (int)sizeof(T), 0x00020000);
+  T v[4 + 2 * R];
+#pragma unroll
+  for (int t = 0; t < 4 + 2 * R; ++t) {
+    const uint32_t off = (uint32_t)((x0 - R + t) * (int)sizeof(T));  // negative wraps out of range
+    if constexpr (sizeof(T) == 4)
+      v[t] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    else {
+      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+      v[t] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    }
+  }
+  T c[2 * R + 1];
+#pragma unroll
+  for (int t = 0; t <= 2 * R; ++t) c[t] = w[t];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (x0 + k >= nx) break;
+    T acc = (T)0;
+#pragma unroll
+    for (int t = 0; t <= 2 * R; ++t) acc = fma_t<T>(c[t], v[k + t], acc);
+    out[x0 + k] = acc;
+  }
+}
+
 template <typename T, bool SKIPZ>
 static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, int nz, int ny, int nx,
                                   const void* w, int seg_h, hipStream_t s) {
@@ -311,7 +344,16 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
   const T* pin = static_cast<const T*>(in);
   T* pout = static_cast<T*>(out);
   const T* pw = static_cast<const T*>(w);
-  if (ndim == 2) {
+  if (ndim == 1) {
+    const dim3 grid((nx + 1023) / 1024), block(256);
+    switch (r) {
+#define SPIDER_D1(RV) \
+  case RV: hipLaunchKernelGGL((direct1d_kernel<T, RV>), grid, block, 0, s, pin, pout, nx, pw); break;
+      SPIDER_D1(1) SPIDER_D1(2) SPIDER_D1(3) SPIDER_D1(4) SPIDER_D1(5) SPIDER_D1(6) SPIDER_D1(7)
+#undef SPIDER_D1
+      default: return hipErrorInvalidValue;
+    }
+  } else if (ndim == 2) {
     const int nseg = (ny + seg_h - 1) / seg_h;
     const dim3 grid(nstrips * nseg), block(64);
     switch (r) {

@@ -77,6 +77,19 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
   return (int)h;
 }
 
+// Blocks per wave of the 1-D band kernel: one resident round of waves, at least 8
+// blocks (the staging depth) per wave.
+static int auto_tile_h_1d(const spider_plan_s* p) {
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  const long long slots = (long long)ncu * 16;
+  const long long nblk = (p->nx + 8 + kStripW - 1) / kStripW;
+  return (int)std::max<long long>(8, (nblk + slots - 1) / slots);
+}
+
 // Planes per wave segment of the 3-D band kernel: one resident round over
 // (strip, 4-line y block, z segment) work units, at least 8 planes deep.
 static int auto_tile_h_3d(const spider_plan_s* p) {
@@ -119,6 +132,11 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
   if (p->engine == SPIDER_ENGINE_DIRECT) {
     e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, p->has_zero_tap, src, dst, p->nz, p->ny, p->nx,
                       p->d_coeffs, p->tile_h, s);
+  } else if (p->ndim == 1) {
+    BandGrid g = p->grid_template;
+    g.in = src;
+    g.out = dst;
+    e = launch_band1d(p->r, p->operand, p->engine, g, s);
   } else if (p->band_h == 8) {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -248,7 +266,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   if (!out) return fail(SPIDER_ERR_INVALID, "out is NULL");
   *out = nullptr;
   if (!coeffs || !shape) return fail(SPIDER_ERR_INVALID, "coeffs or shape is NULL");
-  if (ndim != 2 && ndim != 3) return fail(SPIDER_ERR_INVALID, "ndim must be 2 or 3 (got %d)", ndim);
+  if (ndim < 1 || ndim > 3) return fail(SPIDER_ERR_INVALID, "ndim must be 1, 2 or 3 (got %d)", ndim);
   if (radius < 1 || radius > 7) return fail(SPIDER_ERR_INVALID, "radius must be in 1..7 (got %d)", radius);
   for (int i = 0; i < ndim; ++i)
     if (shape[i] < 1 || shape[i] >= (1LL << 31)) return fail(SPIDER_ERR_INVALID, "shape[%d] out of range", i);
@@ -256,6 +274,9 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   spider_opts_default(&o);
   if (opts) o = *opts;
   if (o.carry < SPIDER_F64 || o.carry > SPIDER_BF16) return fail(SPIDER_ERR_INVALID, "bad carry dtype %d", o.carry);
+  // buffer resources address up to two lines with 32-bit offsets
+  if ((int64_t)shape[ndim - 1] * (int64_t)dtype_bytes(o.carry) >= (1LL << 30))
+    return fail(SPIDER_ERR_UNSUPPORTED, "a line of %lld points is too long", (long long)shape[ndim - 1]);
   int engine = o.engine;
   const bool low = (o.carry == SPIDER_F16 || o.carry == SPIDER_BF16);
   if (engine == SPIDER_ENGINE_AUTO) engine = low ? SPIDER_ENGINE_SPARSE : SPIDER_ENGINE_DIRECT;
@@ -290,7 +311,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   p->ndim = ndim;
   p->r = radius;
   p->nz = ndim == 3 ? (int)shape[0] : 1;
-  p->ny = (int)shape[ndim - 2];
+  p->ny = ndim >= 2 ? (int)shape[ndim - 2] : 1;
   p->nx = (int)shape[ndim - 1];
   p->carry = o.carry;
   p->operand = low ? o.carry : (o.operand ? o.operand : SPIDER_F16);
@@ -301,7 +322,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   const bool pair_ok = matrix && ndim == 2 && radius <= 3 && shape[1] < (1LL << 28);
   p->band_h = (o.band_height == 8 || (o.band_height == 0 && pair_ok)) ? 8 : 16;
   const int kw = 2 * radius + 1;
-  const int ncoef = ndim == 2 ? kw * kw : kw * kw * kw;
+  const int ncoef = ndim == 1 ? kw : (ndim == 2 ? kw * kw : kw * kw * kw);
   p->coeffs.assign(coeffs, coeffs + ncoef);
   for (double c : p->coeffs)
     if (!std::isfinite(c)) {
@@ -330,7 +351,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       spider_plan_destroy(p);
       return hip_fail(e, "coefficient upload");
     }
-    p->nrows = ndim == 2 ? kw : kw * kw;
+    p->nrows = ndim == 1 ? 1 : (ndim == 2 ? kw : kw * kw);
     p->has_zero_tap = false;
     for (double c : p->coeffs) p->has_zero_tap |= (c == 0.0);
     p->tile_h = o.tile_h ? o.tile_h : auto_tile_h_direct(p);
@@ -338,7 +359,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     // Offline transformation, one kernel row (line of taps along x) at a time, or
     // (paired-line bands) one instruction of r + 1 per input line pair.
     const bool pair = p->band_h == 8;
-    const int nrows = pair ? radius + 1 : (ndim == 2 ? kw : kw * kw);
+    const int nrows = pair ? radius + 1 : (ndim == 1 ? 1 : (ndim == 2 ? kw : kw * kw));
     p->nrows = nrows;
     std::vector<PackedRow> rows(nrows);
     std::vector<uint32_t> ipack(((nrows + 1) / 2) * 64, 0u);
@@ -374,7 +395,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       spider_plan_destroy(p);
       return hip_fail(e, "operand upload");
     }
-    p->tile_h = o.tile_h ? o.tile_h : (ndim == 2 ? auto_tile_h_2d(p) : auto_tile_h_3d(p));
+    p->tile_h = o.tile_h ? o.tile_h : (ndim == 1 ? auto_tile_h_1d(p) : ndim == 2 ? auto_tile_h_2d(p) : auto_tile_h_3d(p));
     if (pair) p->tile_h = std::min(p->tile_h + (p->tile_h & 1), p->ny + (p->ny & 1));  // pairs start on even rows
     BandGrid& g = p->grid_template;
     std::memset(&g, 0, sizeof(g));
@@ -383,19 +404,22 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     g.nx = p->nx;
     g.seg_h = p->tile_h;
     g.nstrips = pair ? (p->nx + kPairWinLead + kStripWPair - 1) / kStripWPair
-                     : (ndim == 2 ? (p->nx + 8 + kStripW - 1) / kStripW : (p->nx + kStripW - 1) / kStripW);
+                     : (ndim <= 2 ? (p->nx + 8 + kStripW - 1) / kStripW : (p->nx + kStripW - 1) / kStripW);
     g.apack = static_cast<const uint4*>(p->d_apack);
     g.ipack = static_cast<const uint32_t*>(p->d_ipack);
     g.dpack = static_cast<const uint4*>(p->d_dpack);
     g.rowmask = mask;
-    if (ndim == 2) {
+    if (ndim == 1) {
+      g.nsegs_y = (g.nstrips + p->tile_h - 1) / p->tile_h;  // waves, each streaming tile_h blocks
+      g.nsegs_z = 1;
+    } else if (ndim == 2) {
       g.nsegs_y = (p->ny + p->tile_h - 1) / p->tile_h;
       g.nsegs_z = 1;
     } else {
       g.nsegs_y = (p->ny + kRowsY3 - 1) / kRowsY3;
       g.nsegs_z = (p->nz + p->tile_h - 1) / p->tile_h;
     }
-    g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
+    g.nblocks = ndim == 1 ? g.nsegs_y : g.nstrips * g.nsegs_y * g.nsegs_z;
     // Inside a batched launch the other grids fill the device, so work units can be
     // taller than the single-launch height (their per-unit prologue and halo are
     // amortised over more lines): at least 64 lines (2-D) or 16 planes (3-D).

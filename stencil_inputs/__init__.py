@@ -199,6 +199,16 @@ def workload(name, small=False):
         return dict(name=name, ndim=3, r=1, kind="star", coeffs=w, shape=shape, steps=steps,
                     make_grid=lambda dt=np.float32, s=shape: grid_uniform01(s, 6, dt),
                     seeds=dict(coeffs=None, grid=6))
+    if name in ("1d3p_10240000", "1d5p_10240000"):
+        # the paper's 1-D benchmarks: r = 1 and r = 2 on (1, 10 240 000); it states no step
+        # count or coefficient recipe, so: U[0,1) taps normalised to sum 1, U[0,1) values, 100 steps
+        r = 1 if name.startswith("1d3p") else 2
+        w = coeffs_uniform01(1, r, 7 + r)
+        shape = (50000,) if small else (10240000,)
+        steps = 20 if small else 100
+        return dict(name=name, ndim=1, r=r, kind="box", coeffs=w, shape=shape, steps=steps,
+                    make_grid=lambda dt=np.float32, s=shape: grid_uniform01(s, 8, dt),
+                    seeds=dict(coeffs=7 + r, grid=8))
     raise KeyError(name)
 
 

@@ -1,0 +1,131 @@
+"""GPU parity of 1-D stencils (the paper's 1-D benchmarks: r = 1, 2 on 10 240 000 points).
+
+The 16-point band engine applies the single kernel row to consecutive 256-point
+blocks of the line, each reading its window from the same array (the halo is the
+neighbouring values, zero only beyond the ends).  Integer cases are compared bit
+for bit with the oracle; the workload recipes within the stated tolerances.
+"""
+import numpy as np
+import pytest
+
+import paper_2506_22035_amd as sp
+import stencil_inputs as si
+from gpu_helpers import empty_like_dev, from_dev, rel_errors, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f64": (1e-13, 1e-13)}
+# The 100-step runs at full size: a 16-bit carry rounds every step.  RNE to fp16 of
+# values in [0.5, 1) errs by at most 2^-12 relative (RMS 2^-11 / sqrt(12) ~ 1.4e-4);
+# accumulated coherently over 100 steps: rel-RMS <= 1.4e-2, rel-max <= 2.5e-2.
+TOL_100_STEPS_F16 = (1.4e-2, 2.5e-2)
+LENGTHS = [1, 7, 255, 256, 257, 4096, 10001, 50000, 123457]
+
+
+def run(plan, x_dev, steps):
+    y = empty_like_dev(x_dev)
+    plan.apply(x_dev, y, steps)
+    return from_dev(y)
+
+
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_integer_exact_f16(oracle_mod, engine, n):
+    for r in (1, 2, 3, 5, 7):
+        w = si.integer_coeffs(1, r, -4, 4, 60 + r)
+        x = si.grid_integer((n,), -8, 8, 70 + n % 97)
+        xd, x64 = to_dev(x, "f16")
+        plan = sp.Plan(w, (n,), carry="f16", engine=engine)
+        got = run(plan, xd, 1)
+        ref = oracle_mod.apply(w, x64, 1)
+        assert np.array_equal(got, ref), (r, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+def test_integer_exact_bf16_and_multistep(oracle_mod, engine):
+    n = 30001
+    for r in (1, 2):
+        w = si.integer_coeffs(1, r, -2, 2, 80 + r)
+        xd, x64 = to_dev(si.grid_integer((n,), -2, 2, 81), "bf16")
+        plan = sp.Plan(w, (n,), carry="bf16", engine=engine)
+        assert np.array_equal(run(plan, xd, 1), oracle_mod.apply(w, x64, 1))
+        w = si.integer_coeffs(1, r, -1, 1, 90 + r)
+        xd, x64 = to_dev(si.grid_integer((n,), -2, 2, 91), "f16")
+        plan = sp.Plan(w, (n,), carry="f16", engine=engine)
+        for steps in (2, 3, 4):
+            ref = oracle_mod.apply(w, x64, steps)
+            if np.abs(ref).max() < 2048:
+                assert np.array_equal(run(plan, xd, steps), ref), (r, steps)
+
+
+@pytest.mark.parametrize("carry", ["f16", "bf16"])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("name", ["1d3p_10240000", "1d5p_10240000"])
+def test_workload_tolerance(oracle_mod, carry, engine, name):
+    wl = si.workload(name, small=True)
+    xd, x64 = to_dev(wl["make_grid"](), carry)
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, engine=engine)
+    rms, mx = rel_errors(run(plan, xd, wl["steps"]), oracle_mod.apply(wl["coeffs"], x64, wl["steps"]))
+    print("%s %s %s: rel-RMS %.3e rel-max %.3e" % (name, carry, engine, rms, mx))
+    assert rms <= TOL[carry][0] and mx <= TOL[carry][1]
+
+
+@pytest.mark.parametrize("carry", ["f32", "f64"])
+@pytest.mark.parametrize("n", [1, 13, 4096, 50001])
+def test_direct_engine(oracle_mod, carry, n):
+    for r in (1, 2, 4):
+        rng = np.random.default_rng(n + r)
+        w = rng.uniform(-1, 1, 2 * r + 1) / (2 * r + 1)
+        xd, x64 = to_dev(rng.uniform(-1, 1, n), carry)
+        plan = sp.Plan(w, (n,), carry=carry)
+        assert plan.info()["engine"] == "direct"
+        rms, mx = rel_errors(run(plan, xd, 5), oracle_mod.apply(w, x64, 5))
+        assert rms <= TOL[carry][0] and mx <= TOL[carry][1], r
+
+
+def test_tile_heights_agree_and_aliasing(oracle_mod):
+    import torch
+    wl = si.workload("1d5p_10240000", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    res = []
+    for th in (0, 1, 3, 8, 9, 64, 1000):
+        plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", tile_h=th)
+        res.append(run(plan, xd, 6))
+    for r_ in res[1:]:
+        assert np.array_equal(r_, res[0])
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+    keep = xd.clone()
+    for steps in (0, 1, 2, 3):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), run(plan, xd, steps))
+    assert torch.equal(xd, keep)
+
+
+@pytest.mark.parametrize("name", ["1d3p_10240000", "1d5p_10240000"])
+def test_full_size_sampled(oracle_mod, name):
+    # 10 240 000 points, 100 steps, in the benchmark's configuration; the oracle runs
+    # each sampled point on its dependency cone
+    wl = si.workload(name)
+    xd, x64 = to_dev(wl["make_grid"](), "f16")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+    got = run(plan, xd, wl["steps"])
+    n, h = wl["shape"][0], wl["steps"] * wl["r"]
+    rng = np.random.default_rng(5)
+    pts = [0, 1, n - 1, n - 2, 255, 256, 5119999] + [int(v) for v in rng.integers(0, n, 20)]
+    ref = []
+    for p in pts:
+        a, b = max(0, p - h), min(n, p + h + 1)
+        ref.append(oracle_mod.apply(wl["coeffs"], x64[a:b], wl["steps"])[p - a])
+    rms, mx = rel_errors(np.array([got[p] for p in pts]), np.array(ref))
+    print("%s full size sampled rel-RMS %.3e rel-max %.3e" % (name, rms, mx))
+    assert rms <= TOL_100_STEPS_F16[0] and mx <= TOL_100_STEPS_F16[1]
+
+
+def test_batch_rejects_1d():
+    import torch
+    plan = sp.Plan(np.array([0.25, 0.5, 0.25]), (1000,), carry="f16")
+    x = torch.zeros(1000, dtype=torch.float16, device="cuda:0")
+    with pytest.raises(sp.SpiderError) as e:
+        sp.apply_batch([plan], [x], [torch.empty_like(x)], [3])
+    assert e.value.status == 2

@@ -342,6 +342,9 @@ def test_invalid_arguments_rejected_without_gpu():
     h = ctypes.c_void_p()
     assert L.spider_plan(None, 2, shp, 1, None, ctypes.byref(h)) == 1
     assert L.spider_plan(w.ctypes.data, 4, shp, 1, None, ctypes.byref(h)) == 1
+    assert L.spider_plan(w.ctypes.data, 0, shp, 1, None, ctypes.byref(h)) == 1
+    long_line = (ctypes.c_int64 * 1)(1 << 29)   # 2^29 fp16 points = 2^30 bytes: too long
+    assert L.spider_plan(w.ctypes.data, 1, long_line, 1, None, ctypes.byref(h)) == 2
     assert L.spider_plan(w.ctypes.data, 2, shp, 0, None, ctypes.byref(h)) == 1
     assert L.spider_plan(w.ctypes.data, 2, shp, 8, None, ctypes.byref(h)) == 1
     bad = (ctypes.c_int64 * 2)(0, 64)
