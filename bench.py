@@ -141,6 +141,54 @@ def serving(torch, sp, si, n, fractions, seed=11):
     return out
 
 
+def batch3d(torch, sp, si, args):
+    """Box-3D27P 512^3 and Heat-3D 256^3, 20 steps each, advanced together by the
+    batched kernel (one launch per time step covering both grids), fp16
+    carry; compared with the two grids run one after the other on their own plans."""
+    wls = [si.workload("box3d27p_512"), si.workload("heat3d_256")]
+    xs = [torch.from_numpy(wl["make_grid"](np.float32)).to(torch.float16).to("cuda:0") for wl in wls]
+    ys = [torch.empty_like(x) for x in xs]
+    plans = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True) for wl in wls]
+    steps = [wl["steps"] for wl in wls]
+    npts = sum(int(np.prod(wl["shape"])) * wl["steps"] for wl in wls)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sp.apply_batch(plans, xs, ys, steps)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for k in range(args.steps):
+        sp.apply_batch(plans, xs, ys, steps)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    total = evs[0].elapsed_time(evs[-1])
+    # the same work, each grid alone on its own plan (one step per launch, as batched)
+    solo = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True, time_block=1) for wl in wls]
+    for p, x, y, st in zip(solo, xs, ys, steps):
+        p.apply(x, y, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        for p, x, y, st in zip(solo, xs, ys, steps):
+            p.apply(x, y, st)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1) / args.steps
+    value = npts * args.steps / (total * 1e-3) / 1e9
+    return {"metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(total / args.steps, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+            "config": {"workload": "batch3d: box3d27p 512^3 x 20 steps + heat3d 256^3 x 20 steps, one batched "
+                                   "launch per time step", "carry": "f16", "engine": "sparse"},
+            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
+                           "p99": round(float(np.percentile(per, 99)), 4)},
+            "separate_plans": {"ms_per_step": round(seq_ms, 4),
+                               "GStencil/s": round(npts / (seq_ms * 1e-3) / 1e9, 2),
+                               "tile_h": [p.info()["tile_h"] for p in solo]}}
+
+
 def size_trend(torch, sp, si, args):
     """Throughput versus grid size for the Box-2D49P stencil (the paper's size trend, Fig. 11):
     square grids of the headline recipe's stencil and field, 50 steps per pass, fp16 carry."""
@@ -170,7 +218,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="box2d49p_10240",
                     choices=["box2d49p_10240", "star2d13p_8192", "box2d9p_256_f64", "box3d27p_512", "heat3d_256",
-                             "1d3p_10240000", "1d5p_10240000"],
+                             "1d3p_10240000", "1d5p_10240000", "batch3d"],
                     help="workload recipe (default: the headline Box-2D49P)")
     ap.add_argument("--carry", default=None, choices=["f16", "bf16", "f32", "f64"],
                     help="grid dtype (default f16; f64 for box2d9p_256_f64)")
@@ -207,6 +255,10 @@ def main():
 
     if args.trend:
         print(json.dumps(size_trend(torch, sp, si, args)))
+        return
+
+    if args.workload == "batch3d":
+        print(json.dumps(batch3d(torch, sp, si, args)))
         return
 
     if args.serving:

@@ -52,6 +52,8 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
 // One launch of the two-step kernel (requires time_block == 2).
 spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
 void set_tile2(spider_plan_s* p, int h);
+// Geometry of the plan's work units inside batched launches (from its current tile height).
+void set_batch_geometry(spider_plan_s* p);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
 // Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).
 spider_status autotune_tile(spider_plan_s* p);

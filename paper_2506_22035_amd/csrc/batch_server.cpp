@@ -1,9 +1,12 @@
 // Batched time loop over many grids and the continuous-batching server.
 //
 // Batching is not in the paper (it evaluates one grid at a time); it serves
-// many grids of uneven size and stencil shape with one persistent launch per
-// time step, every workgroup pulling (grid, strip, segment) work units from a
-// device counter.  The server admits requests by device footprint and free
+// many grids of uneven size and stencil shape with one launch per time step,
+// one workgroup per (grid, strip, segment) work unit, each workgroup finding
+// its grid by binary search over the units' prefix sums.  (A persistent
+// variant, in which resident workgroups pulled units from device counters,
+// measured up to 1.5x slower: the hardware dispatcher hands out work units
+// more cheaply than returning atomics do.)  The server admits requests by device footprint and free
 // slots, advances all admitted requests together in rounds of batched steps,
 // and lets requests that arrive meanwhile join at the next round.
 #include <hip/hip_runtime.h>
@@ -95,8 +98,59 @@ static int batch_kind(const spider_plan_s* p) {
 
 static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+static int device_cus() {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int ncu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  cache.emplace(dev, ncu);
+  return ncu;
+}
+
+static void set_height_3d(BandGrid& g, int h) {
+  h = std::min(h, g.nz);
+  g.seg_h = h;
+  g.nsegs_z = (g.nz + h - 1) / h;
+  g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
+}
+
+// Segment height (planes) shared by the 3-D grids of one batch.  Tall segments
+// re-read fewer halo planes, and equal heights give units of similar length
+// (a launch lasts as long as its longest units), but the launch still needs
+// 4 units per CU to fill the device: the tallest height up to 64 planes for
+// which the batch's first step has that many units.
+static int batch_height_3d(const std::vector<BatchItem>& items) {
+  long long fixed = 0;
+  bool any3 = false;
+  for (const auto& it : items) {
+    if (it.steps <= 0) continue;
+    if (it.plan->ndim == 3) any3 = true;
+    else fixed += it.plan->grid_batch.nblocks;
+  }
+  if (!any3) return 64;
+  const long long want = 4LL * device_cus();
+  for (int h = 64; h > 1; --h) {
+    long long units = fixed;
+    for (const auto& it : items) {
+      if (it.steps <= 0 || it.plan->ndim != 3) continue;
+      BandGrid g = it.plan->grid_batch;
+      set_height_3d(g, h);
+      units += g.nblocks;
+    }
+    if (units >= want) return h;
+  }
+  return 1;
+}
+
 // Enqueue the batched time loop of `items` on stream s.
-spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, hipStream_t s, int nwg_cap) {
+
+spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, hipStream_t s) {
   const int n = (int)items.size();
   int operand = -1, engine = -1, maxsteps = 0;
   for (const auto& it : items) {
@@ -114,6 +168,9 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     if (it.steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
     maxsteps = std::max(maxsteps, it.steps);
   }
+  // the kernel variant holding only the body classes present (2-D: 1, 3-D: 2)
+  int cls = 0;
+  for (const auto& it : items) cls |= it.plan->ndim == 3 ? 2 : 1;
   // Per item: the first source, after the in == out copy when needed.
   std::vector<const void*> src(n);
   for (int i = 0; i < n; ++i) {
@@ -132,8 +189,8 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     }
   }
   if (maxsteps == 0) return SPIDER_OK;
-  // Descriptor layout per step: BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned,
-  // then one counter per step.
+  const int h3 = batch_height_3d(items);
+  // Descriptor layout per step: BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned.
   std::vector<size_t> off(maxsteps + 1);
   std::vector<int> m(maxsteps);
   size_t bytes = 0;
@@ -145,8 +202,6 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     bytes += align_up(cnt * sizeof(BandGrid) + cnt * sizeof(int) + (cnt + 1) * sizeof(int), 256);
   }
   off[maxsteps] = bytes;
-  const size_t counters_off = bytes;
-  bytes += align_up(maxsteps * sizeof(int), 256);
 
   std::lock_guard<std::mutex> lk(A.mu);
   hipError_t e = A.reserve(bytes);
@@ -165,6 +220,7 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
       const int k = st + 1;
       void* dst = ((it.steps - k) % 2 == 0) ? it.out : it.scratch;
       BandGrid g = it.plan->grid_batch;
+      if (it.plan->ndim == 3) set_height_3d(g, h3);
       g.in = cur[i];
       g.out = dst;
       cur[i] = dst;
@@ -177,34 +233,21 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     begin[j] = acc;
     units[st] = acc;
   }
-  e = hipMemcpyAsync(A.dev, A.host, counters_off, hipMemcpyHostToDevice, s);
+  e = hipMemcpyAsync(A.dev, A.host, bytes, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-  int* counters = reinterpret_cast<int*>(A.dev + counters_off);
-  e = launch_zero_ints(counters, maxsteps, s);
-  if (e != hipSuccess) return hip_fail(e, "counter reset");
   for (int st = 0; st < maxsteps; ++st) {
     char* base = A.dev + off[st];
     const BandGrid* gd = reinterpret_cast<const BandGrid*>(base);
     const int* kinds = reinterpret_cast<const int*>(base + m[st] * sizeof(BandGrid));
     const int* begin = kinds + m[st];
-    const int nwg = std::max(1, std::min(units[st], nwg_cap));
-    e = launch_band_batch(operand, engine, gd, kinds, begin, m[st], counters + st, nwg, s);
+    if (units[st] < 1) return fail(SPIDER_ERR_INVALID, "batch step without work units");
+    e = launch_band_batch(operand, engine, cls, gd, kinds, begin, m[st], units[st], s);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   }
   e = hipEventRecord(A.done, s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   A.pending = true;
   return SPIDER_OK;
-}
-
-static int batch_nwg_cap(int operand, int engine) {
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-  }
-  int per = band_batch_blocks_per_cu(operand, engine);
-  return ncu * std::max(per, 1);
 }
 
 static BatchArena& global_arena() {
@@ -301,7 +344,6 @@ void finish(spider_server_s* S, ServerRequest* r, spider_status st) {
 
 void server_loop(spider_server_s* S) {
   hipSetDevice(S->device);
-  std::map<int, int> caps;  // resident workgroups of the batch kernel per (operand, engine)
   for (;;) {
     std::vector<ServerRequest*> round;
     {
@@ -338,10 +380,7 @@ void server_loop(spider_server_s* S) {
     }
     spider_status st = SPIDER_OK;
     for (auto& kv : groups) {
-      auto c = caps.find(kv.first);
-      if (c == caps.end())
-        c = caps.emplace(kv.first, spider_impl::batch_nwg_cap(kv.first / 8, kv.first % 8)).first;
-      st = spider_impl::enqueue_batch(S->arena, kv.second, S->stream, c->second);
+      st = spider_impl::enqueue_batch(S->arena, kv.second, S->stream);
       if (st != SPIDER_OK) break;
     }
     if (st == SPIDER_OK && hipStreamSynchronize(S->stream) != hipSuccess) st = SPIDER_ERR_HIP;
@@ -384,8 +423,7 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
     }
     items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
-  const int cap = batch_nwg_cap(plans[0]->operand, plans[0]->engine);
-  return enqueue_batch(global_arena(), items, static_cast<hipStream_t>(stream), cap);
+  return enqueue_batch(global_arena(), items, static_cast<hipStream_t>(stream));
 }
 
 spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue, spider_server_t* out) {

@@ -78,25 +78,21 @@ int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
 int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);
 
 // ------------------------------------------------------------------ batched launch
-// Body selected per grid inside the persistent batch kernel.
+// Body selected per grid inside the batch kernel.
 enum BatchKind : int {
   kB2dR1 = 0, kB2dR2 = 1, kB2dR3 = 2, kB3dBox = 3, kB3dStar = 4,
   kB2dPairR1 = 5, kB2dPairR2 = 6, kB2dPairR3 = 7  // paired-line bands (one step)
 };
 
-// One persistent launch advancing every listed grid by one time step.
+// One launch advancing every listed grid by one time step.
 //   grids    device array of n BandGrid (in/out already set for this step)
 //   kinds    device array of n BatchKind
 //   begin    device array of n+1 prefix sums of grids[i].nblocks
-//   counter  device int, zero before the launch (work-queue cursor)
-// nwg workgroups loop over the begin[n] work units, each taking the next unit
-// from the counter until none is left.
-hipError_t launch_band_batch(int operand, int engine, const BandGrid* grids, const int* kinds, const int* begin, int n,
-                             int* counter, int nwg, hipStream_t s);
-// Resident workgroups per CU of the batch kernel.
-int band_batch_blocks_per_cu(int operand, int engine);
-// Zero `n` ints on the stream with a small kernel (safe inside graph capture).
-hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+//   units    begin[n] (host copy): one workgroup per work unit
+// cls: bodies compiled into the launched kernel, 1 = 2-D kinds only, 2 = 3-D kinds
+// only, 3 = both (a batch of one class gets a smaller register budget per wave).
+hipError_t launch_band_batch(int operand, int engine, int cls, const BandGrid* grids, const int* kinds,
+                             const int* begin, int n, int units, hipStream_t s);
 
 // Output rows per 3-D wave along y (accumulator block height).
 constexpr int kRowsY3 = 4;

@@ -679,40 +679,39 @@ int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned) {
 
 // ----------------------------------------------------------------------------- batched
 
-template <int OP, int ENG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void band_batch_kernel(
-    const BandGrid* __restrict__ grids, const int* __restrict__ kinds, const int* __restrict__ begin, int n,
-    int* __restrict__ counter) {
-  // the largest body: 16-point 2-D r = 3 (7 lines + spare) or paired r = 1 / 3 (8 lines)
-  constexpr int kLds16 = 7 * kLdsRowDw + kLdsSpareDw, kLdsPair = 8 * kPairRowDw;
-  constexpr int kLds = kLds16 > kLdsPair ? kLds16 : kLdsPair;
+// One workgroup per work unit (a strip segment of one grid); the launch has
+// exactly begin[n] workgroups.  CLS selects the bodies compiled in: 1 = 2-D
+// kinds, 2 = 3-D kinds, 3 = all.
+template <int OP, int ENG, int CLS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 2 && ENG == 1) ? 3 : 2))) void band_batch_kernel(
+    const BandGrid* __restrict__ grids, const int* __restrict__ kinds, const int* __restrict__ begin, int n) {
+  constexpr bool k2d = (CLS & 1) != 0, k3d = (CLS & 2) != 0;
+  constexpr int kLds = (7 * kLdsRowDw + kLdsSpareDw) > (8 * kPairRowDw) ? (7 * kLdsRowDw + kLdsSpareDw) : (8 * kPairRowDw);
   __shared__ uint32_t lds[kLds];
   const int total = begin[n];
-  for (;;) {
-    int unit = 0;
-    if (threadIdx.x == 0) unit = atomicAdd(counter, 1);
-    unit = __builtin_amdgcn_readfirstlane(__shfl(unit, 0));
-    if (unit >= total) break;  // every wave reaches this exit once the queue is drained
-    // grid owning `unit`: last i with begin[i] <= unit
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (begin[mid] <= unit) lo = mid;
-      else hi = mid - 1;
-    }
-    const BandGrid g = grids[lo];
-    const int w = unit - begin[lo];
-    const bool al = (g.nx % 8) == 0;
-    switch (kinds[lo]) {
-      case kB2dR1:
-        if (al) band2d_body<1, OP, ENG, true>(g, w, lds); else band2d_body<1, OP, ENG, false>(g, w, lds);
-        break;
-      case kB2dR2:
-        if (al) band2d_body<2, OP, ENG, true>(g, w, lds); else band2d_body<2, OP, ENG, false>(g, w, lds);
-        break;
-      case kB2dR3:
-        if (al) band2d_body<3, OP, ENG, true>(g, w, lds); else band2d_body<3, OP, ENG, false>(g, w, lds);
-        break;
+  const int b = blockIdx.x;
+  if (b >= total) return;
+  // Workgroups are dealt round-robin over the 8 XCDs (b % 8); give each XCD a
+  // contiguous range of units, so that neighbouring units, which read the same
+  // halo lines, run under one L2.  The map is a bijection of [0, total).
+  const int q = total >> 3, rem = total & 7, x = b & 7;
+  const int unit = x * q + (x < rem ? x : rem) + (b >> 3);
+  // grid owning `unit`: last i with begin[i] <= unit
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= unit) lo = mid;
+    else hi = mid - 1;
+  }
+  const BandGrid g = grids[lo];
+  const int w = unit - begin[lo];
+  const bool al = (g.nx % 8) == 0;
+  const int kind = kinds[lo];
+  if constexpr (k2d) {
+    switch (kind) {
+      case kB2dR1: if (al) band2d_body<1, OP, ENG, true>(g, w, lds); else band2d_body<1, OP, ENG, false>(g, w, lds); break;
+      case kB2dR2: if (al) band2d_body<2, OP, ENG, true>(g, w, lds); else band2d_body<2, OP, ENG, false>(g, w, lds); break;
+      case kB2dR3: if (al) band2d_body<3, OP, ENG, true>(g, w, lds); else band2d_body<3, OP, ENG, false>(g, w, lds); break;
       case kB2dPairR1:
         if (al) band2d_pair_body<1, OP, ENG, true>(g, w, lds); else band2d_pair_body<1, OP, ENG, false>(g, w, lds);
         break;
@@ -722,54 +721,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ba
       case kB2dPairR3:
         if (al) band2d_pair_body<3, OP, ENG, true>(g, w, lds); else band2d_pair_body<3, OP, ENG, false>(g, w, lds);
         break;
-      case kB3dBox:
-        if (al) band3d_body<1, OP, ENG, true, box_mask3<1>()>(g, w, lds);
-        else band3d_body<1, OP, ENG, false, box_mask3<1>()>(g, w, lds);
-        break;
       default:
-        if (al) band3d_body<1, OP, ENG, true, star_mask3<1>()>(g, w, lds);
-        else band3d_body<1, OP, ENG, false, star_mask3<1>()>(g, w, lds);
         break;
     }
-    wave_lds_sync();  // LDS reuse by the next unit
+  }
+  if constexpr (k3d) {
+    if (kind == kB3dBox) {
+      if (al) band3d_body<1, OP, ENG, true, box_mask3<1>()>(g, w, lds);
+      else band3d_body<1, OP, ENG, false, box_mask3<1>()>(g, w, lds);
+    } else if (kind == kB3dStar) {
+      if (al) band3d_body<1, OP, ENG, true, star_mask3<1>()>(g, w, lds);
+      else band3d_body<1, OP, ENG, false, star_mask3<1>()>(g, w, lds);
+    }
   }
 }
 
-__global__ void zero_ints_kernel(int* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
-hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_band_batch(int operand, int engine, const BandGrid* grids, const int* kinds, const int* begin, int n,
-                             int* counter, int nwg, hipStream_t s) {
-  const dim3 grid(nwg), block(64);
-  if (operand == 2 && engine == 1)
-    hipLaunchKernelGGL((band_batch_kernel<2, 1>), grid, block, 0, s, grids, kinds, begin, n, counter);
-  else if (operand == 2 && engine == 2)
-    hipLaunchKernelGGL((band_batch_kernel<2, 2>), grid, block, 0, s, grids, kinds, begin, n, counter);
-  else if (operand == 3 && engine == 1)
-    hipLaunchKernelGGL((band_batch_kernel<3, 1>), grid, block, 0, s, grids, kinds, begin, n, counter);
-  else if (operand == 3 && engine == 2)
-    hipLaunchKernelGGL((band_batch_kernel<3, 2>), grid, block, 0, s, grids, kinds, begin, n, counter);
+template <int OP, int ENG>
+static hipError_t launch_batch_cls(int cls, const BandGrid* grids, const int* kinds, const int* begin, int n,
+                                   int units, hipStream_t s) {
+  const dim3 grid(units), block(64);
+  if (cls == 1)
+    hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 1>), grid, block, 0, s, grids, kinds, begin, n);
+  else if (cls == 2)
+    hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 2>), grid, block, 0, s, grids, kinds, begin, n);
   else
-    return hipErrorInvalidValue;
+    hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 3>), grid, block, 0, s, grids, kinds, begin, n);
   return hipGetLastError();
 }
 
-int band_batch_blocks_per_cu(int operand, int engine) {
-  int nb = 0;
-  hipError_t e = hipErrorInvalidValue;
-  if (operand == 2 && engine == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<2, 1>, 64, 0);
-  if (operand == 2 && engine == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<2, 2>, 64, 0);
-  if (operand == 3 && engine == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<3, 1>, 64, 0);
-  if (operand == 3 && engine == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band_batch_kernel<3, 2>, 64, 0);
-  return e == hipSuccess ? nb : 0;
+hipError_t launch_band_batch(int operand, int engine, int cls, const BandGrid* grids, const int* kinds,
+                             const int* begin, int n, int units, hipStream_t s) {
+  if (cls < 1 || cls > 3 || units < 1) return hipErrorInvalidValue;
+  if (operand == 2 && engine == 1) return launch_batch_cls<2, 1>(cls, grids, kinds, begin, n, units, s);
+  if (operand == 2 && engine == 2) return launch_batch_cls<2, 2>(cls, grids, kinds, begin, n, units, s);
+  if (operand == 3 && engine == 1) return launch_batch_cls<3, 1>(cls, grids, kinds, begin, n, units, s);
+  if (operand == 3 && engine == 2) return launch_batch_cls<3, 2>(cls, grids, kinds, begin, n, units, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace spider_impl

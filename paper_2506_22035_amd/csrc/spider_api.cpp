@@ -174,6 +174,29 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   return SPIDER_OK;
 }
 
+// Work units inside a batched launch: the plan's one-step segments, but at least
+// 64 lines (2-D) or 16 planes (3-D) tall, since the other grids of the batch help
+// fill the device and taller units amortise their prologue and halo.  1-D plans
+// are not batched.
+void set_batch_geometry(spider_plan_s* p) {
+  p->grid_batch = p->grid_template;
+  if (p->ndim == 1) return;
+  BandGrid& g = p->grid_batch;
+  int hb;
+  if (p->ndim == 2) {
+    // flat in measurements from 32 to 256 rows; 64 keeps the halo share small
+    hb = std::min(p->ny, std::max(p->tile_h, 64));
+    if (p->band_h == 8) hb += hb & 1;
+    g.nsegs_y = (p->ny + hb - 1) / hb;
+  } else {
+    // the batched launch re-chooses one common 3-D height per batch
+    hb = std::min(p->nz, 64);
+    g.nsegs_z = (p->nz + hb - 1) / hb;
+  }
+  g.seg_h = hb;
+  g.nblocks = g.nstrips * g.nsegs_y * g.nsegs_z;
+}
+
 void set_tile2(spider_plan_s* p, int h) {
   if (p->band_h == 8) h += h & 1;  // paired-line bands: segments start on even rows
   p->tile_h2 = h;
@@ -420,20 +443,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       g.nsegs_z = (p->nz + p->tile_h - 1) / p->tile_h;
     }
     g.nblocks = ndim == 1 ? g.nsegs_y : g.nstrips * g.nsegs_y * g.nsegs_z;
-    // Inside a batched launch the other grids fill the device, so work units can be
-    // taller than the single-launch height (their per-unit prologue and halo are
-    // amortised over more lines): at least 64 lines (2-D) or 16 planes (3-D).
-    p->grid_batch = g;
-    {
-      int hb = ndim == 2 ? std::min(p->ny, std::max(p->tile_h, 64)) : std::min(p->nz, std::max(p->tile_h, 16));
-      if (pair) hb += hb & 1;
-      p->grid_batch.seg_h = hb;
-      if (ndim == 2)
-        p->grid_batch.nsegs_y = (p->ny + hb - 1) / hb;
-      else
-        p->grid_batch.nsegs_z = (p->nz + hb - 1) / hb;
-      p->grid_batch.nblocks = p->grid_batch.nstrips * p->grid_batch.nsegs_y * p->grid_batch.nsegs_z;
-    }
+    set_batch_geometry(p);
     // two fused steps per launch: 2-D, radius <= 3, 16-bit carry
     const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair);
     p->time_block = (o.time_block != 1 && tb2_ok) ? 2 : 1;
@@ -450,6 +460,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       spider_plan_destroy(p);
       return st;
     }
+    if (engine != SPIDER_ENGINE_DIRECT) set_batch_geometry(p);  // from the tuned height
   }
   *out = p;
   return SPIDER_OK;
