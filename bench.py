@@ -33,7 +33,7 @@ TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": 
 KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band_pair.hip", "paper_2506_22035_amd/csrc/band_pair.h",
                   "paper_2506_22035_amd/csrc/band_common.h"]
 # the dominant kernel of the headline run: two fused time steps per launch
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_pair_tb2_box49p_f16_10240_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_pair_tbt_box49p_f16_10240_traffic.json")
 
 
 def kernel_source_hash():
@@ -44,14 +44,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch):
-    """HBM bytes per launch from committed rocprofv3 counters, if taken on this kernel source."""
+def measured_traffic(bytes_per_launch, steps_per_launch):
+    """HBM bytes per launch from committed rocprofv3 counters, if taken on this kernel source
+    and the same number of fused steps."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if t.get("time_steps_per_launch") != steps_per_launch or t.get("alg_bytes_per_launch") != bytes_per_launch:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -218,7 +221,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="box2d49p_10240",
                     choices=["box2d49p_10240", "star2d13p_8192", "box2d9p_256_f64", "box3d27p_512", "heat3d_256",
-                             "1d3p_10240000", "1d5p_10240000", "batch3d"],
+                             "1d3p_10240000", "1d5p_10240000", "box2d7r_10240", "batch3d"],
                     help="workload recipe (default: the headline Box-2D49P)")
     ap.add_argument("--carry", default=None, choices=["f16", "bf16", "f32", "f64"],
                     help="grid dtype (default f16; f64 for box2d9p_256_f64)")
@@ -229,8 +232,11 @@ def main():
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--band-height", type=int, default=0, choices=[0, 8, 16],
                     help="output points per band row (0: the library's choice)")
-    ap.add_argument("--time-block", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--time-block", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="time steps fused per launch (0: the library's choice)")
+    ap.add_argument("--row-swap", default="implicit", choices=["implicit", "explicit"],
+                    help="row swap in the gather offsets (implicit) or by an LDS copy (explicit; the comparison "
+                         "of the paper's Table 3: sparse engine, band height 16, one step per launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip errors, fp32 path and ablation")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -290,7 +296,8 @@ def main():
 
     t0 = time.perf_counter()
     plan = sp.Plan(wl["coeffs"], wl["shape"], carry=args.carry, engine=args.engine, split=args.split,
-                   tile_h=args.tile_h, autotune=True, band_height=args.band_height, time_block=args.time_block)
+                   tile_h=args.tile_h, autotune=True, band_height=args.band_height, time_block=args.time_block,
+                   row_swap=args.row_swap)
     plan_ms = (time.perf_counter() - t0) * 1e3
     info = plan.info()
 
@@ -303,31 +310,56 @@ def main():
     ms_per_step = total_ms / args.steps
     value = npts * T * args.steps / (total_ms * 1e-3) / 1e9
 
-    # Roofline of the dominant kernel.  A launch of the two-step kernel advances two
-    # time steps; the algorithmic bytes are one read and one write of the state per
-    # point and time step, so a fused launch is charged for both steps.
+    # Roofline of the dominant kernel.  A fused launch advances tb time steps; the
+    # algorithmic bytes are one read and one write of the state per point and time
+    # step, so a fused launch is charged for all of its steps.
     tb = info["time_block"]
     fused = T // tb                       # launches of the dominant kernel per pass
-    launches = args.steps * fused
     steps_per_launch = tb
-    avg_launch_s = total_ms * 1e-3 / (args.steps * (fused + T % tb))
+    if T % tb == 0:
+        # every launch of the pass is the dominant kernel: its average over the timed region
+        avg_launch_s = total_ms * 1e-3 / (args.steps * fused)
+        launch_timing = "timed region"
+    else:
+        # a pass ends with T % tb single steps: time the fused kernel on its own, one
+        # launch per apply of tb steps, HIP events on the same stream
+        n_l = max(10, args.steps * fused)
+        le0, le1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        yl = torch.empty_like(xd)  # y keeps the timed passes' result for the error check
+        plan.apply(xd, yl, tb, stream=stream)
+        le0.record(stream)
+        for _ in range(n_l):
+            plan.apply(xd, yl, tb, stream=stream)
+        le1.record(stream)
+        torch.cuda.synchronize()
+        del yl
+        avg_launch_s = le0.elapsed_time(le1) * 1e-3 / n_l
+        launch_timing = "%d single launches after the timed region" % n_l
     elem = {"f16": 2, "bf16": 2, "f32": 4, "f64": 8}[args.carry]
     alg_bytes = npts * 2 * elem * steps_per_launch
     achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic(alg_bytes) if headline and args.carry == "f16" and args.engine == "sparse" else None
-    _ = launches
+    traffic = measured_traffic(alg_bytes, tb) if headline and args.carry == "f16" and args.engine == "sparse" else None
+    rr = (wl["coeffs"].shape[0] - 1) // 2
+    if args.engine == "direct":
+        kname = "direct%dd_kernel" % len(shape)
+    elif args.carry == "f32":
+        kname = ("band2d_pair_f32_kernel<fused>" if tb == 2 else
+                 "band2d_pair_f32_kernel" if info["band_height"] == 8 else "band2d_f32_kernel")
+    elif len(shape) != 2:
+        kname = "band%dd_kernel" % len(shape)
+    elif info["band_height"] == 8:
+        kname = {1: "band2d_pair_kernel", 2: "band2d_pair_tb2_kernel"}.get(tb, "band2d_pair_tbt_kernel")
+    else:
+        kname = "band2d_tb2_kernel" if tb == 2 else "band2d_kernel"
+    kname += "<r=%d,%s,%s%s%s>" % (rr, args.carry, args.engine, ",T=%d" % tb if tb > 2 else "",
+                                   ",explicit row swap" if args.row_swap == "explicit" else "")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": ("direct%dd_kernel" if args.engine == "direct" else
-                       ("band%dd_pair_f32_kernel<fused>" if (args.carry == "f32" and tb == 2) else
-                        ("band%dd_pair_f32_kernel" if (args.carry == "f32" and info["band_height"] == 8) else
-                         ("band%dd_f32_kernel" if args.carry == "f32" else
-                          ("band%dd_pair" if info["band_height"] == 8 else "band%dd")
-                          + ("_tb2_kernel" if tb == 2 else "_kernel"))))) % len(shape)
-                      + "<r=%d,%s,%s>" % ((wl["coeffs"].shape[0] - 1) // 2, args.carry, args.engine),
+            "kernel": kname,
             "time_steps_per_launch": steps_per_launch,
             "alg_bytes_per_launch": alg_bytes,
-            "avg_launch_us": round(avg_launch_s * 1e6, 2)}
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+            "launch_timing": launch_timing}
 
     # a plain device copy of the same grid: read + write of the same bytes, for reference
     z = torch.empty_like(xd)
@@ -352,7 +384,7 @@ def main():
                       "engine": info["engine"], "split": args.split if args.engine != "direct" else None,
                       "tile_h": info["tile_h"],
                       "time_steps_per_launch": info["time_block"], "tile_h2": info["tile_h2"],
-                      "band_height": info["band_height"],
+                      "band_height": info["band_height"], "row_swap": args.row_swap,
                       "coeff_seed": wl["seeds"]["coeffs"], "grid_seed": wl["seeds"]["grid"]},
            "wall_ms_timed_region": round(wall_ms, 3), "plan_ms": round(plan_ms, 3),
            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),

@@ -77,8 +77,11 @@ typedef struct {
     int time_block; /* time steps fused per launch: 0 = automatic (two for 2-D grids of
                        radius <= 3 on the matrix engines with a 16-bit carry or with
                        paired-line bands, else one),
-                       1 = one step per launch, 2 = two where supported.  Results are
-                       identical bit for bit. */
+                       1 = one step per launch, 2 = two where supported, 3 or 4 = that many
+                       for paired-line bands with a 16-bit carry (else two where
+                       supported, else one).  A time loop of n steps runs n / T fused
+                       launches and then n mod T single steps.  The results agree to
+                       rounding; see band_height for when they are identical. */
     int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16
                       (default, also when 0) or SPIDER_BF16.  With a 16-bit carry the operand
                       is the carry type and this field must be 0 or equal to it. */
@@ -87,9 +90,17 @@ typedef struct {
                         windows (any radius), 8 = the paper's band height L = 2r + 2 <= 8
                         with two output lines per instruction (2-D, radius <= 3, 16-bit or
                         fp32 carry; segment heights are rounded up to even numbers).  The two
-                        give different rounding orders.  With band height 8 and odd r, two
-                        fused steps (time_block 2) round differently from two single
-                        steps; with band height 16 they are identical bit for bit. */
+                        give different rounding orders.  With band height 8 and odd r, fused
+                        steps (time_block >= 2) round differently from single steps; with
+                        even r, or band height 16, they are identical bit for bit. */
+    int row_swap;  /* where the input rows are swapped to match the strided-swapped kernel
+                      matrix (Sec. 3.2): 0 = implicitly, in the gather's LDS offsets (default);
+                      1 = explicitly, by copying each staged line into a swapped operand tile
+                      in LDS first -- the comparison of the paper's Table 3, for measurement.
+                      Same result bit for bit.  1 needs the sparse engine, a 16-bit carry, a
+                      2-D grid and band height 16, and runs one step per launch (band_height
+                      0 resolves to 16, time_block 0 to 1; other values are UNSUPPORTED);
+                      batched apply and the server reject such plans. */
 } spider_opts;
 
 typedef struct spider_plan_s* spider_plan_t;

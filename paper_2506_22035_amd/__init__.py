@@ -33,7 +33,8 @@ class SpiderError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("carry", ctypes.c_int), ("engine", ctypes.c_int), ("split", ctypes.c_int),
                 ("tile_h", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("time_block", ctypes.c_int), ("operand", ctypes.c_int), ("band_height", ctypes.c_int)]
+                ("time_block", ctypes.c_int), ("operand", ctypes.c_int), ("band_height", ctypes.c_int),
+                ("row_swap", ctypes.c_int)]
 
 
 _lib = None
@@ -171,7 +172,7 @@ class Plan:
     operand type of the matrix engines for an "f32" carry.  Owns device memory until `close()`."""
 
     def __init__(self, coeffs, shape, carry="f16", engine="auto", split=2, tile_h=0, use_graph=True, autotune=False,
-                 time_block=0, operand=None, band_height=0):
+                 time_block=0, operand=None, band_height=0, row_swap="implicit"):
         w = np.ascontiguousarray(coeffs, dtype=np.float64)
         ndim = len(shape)
         if w.ndim != ndim or len(set(w.shape)) != 1 or w.shape[0] % 2 != 1:
@@ -190,6 +191,7 @@ class Plan:
         opts.time_block = int(time_block)
         opts.operand = DTYPES[operand] if operand else 0
         opts.band_height = int(band_height)
+        opts.row_swap = {"implicit": 0, "explicit": 1}[row_swap]
         shp = (ctypes.c_int64 * ndim)(*self.shape)
         h = ctypes.c_void_p()
         _check(lib().spider_plan(_ptr(w), ndim, shp, self.radius, ctypes.byref(opts), ctypes.byref(h)))

@@ -19,6 +19,9 @@ struct spider_plan_s {
   int engine = SPIDER_ENGINE_SPARSE;
   int split = 2;
   int band_h = 16;           // output points per band row: 16, or 8 (paired-line bands)
+  int row_swap = 0;          // 1: explicit row swap through an LDS copy (ablation)
+  int max_time_block = 1;    // deepest fusion this plan supports (paired 16-bit: 4)
+  bool tune_depth = false;   // the autotuner also chooses time_block (2..max_time_block)
   int tile_h = 0;
   int use_graph = 1;
   int device = 0;
@@ -33,9 +36,9 @@ struct spider_plan_s {
   void* d_scratch = nullptr;
   size_t grid_bytes = 0;
   spider_impl::BandGrid grid_template{};
-  int time_block = 1;                   // steps fused per launch of the matrix engines (1 or 2)
-  int tile_h2 = 0;                      // segment height of the two-step kernel
-  spider_impl::BandGrid grid_tb2{};     // two-step kernel: 240-wide strips
+  int time_block = 1;                   // steps fused per launch of the matrix engines (1..4)
+  int tile_h2 = 0;                      // segment height of the fused kernel
+  spider_impl::BandGrid grid_tb2{};     // fused kernel: 240-wide strips (two steps) or pair_tb_width
   spider_impl::BandGrid grid_batch{};   // one-step kernel inside batched launches (taller segments)
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
@@ -49,7 +52,10 @@ void clear_err();
 size_t dtype_bytes(int dt);
 spider_status ensure_scratch(spider_plan_s* p);
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
-// One launch of the two-step kernel (requires time_block == 2).
+// Fused steps per launch (1..4) and the fused kernel's geometry for it (strip
+// width and the heuristic segment height, or `tile_h` when non-zero).
+void set_time_block(spider_plan_s* p, int T, int tile_h);
+// One launch of the fused kernel: time_block (2..4) steps.
 spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStream_t s);
 void set_tile2(spider_plan_s* p, int h);
 // Geometry of the plan's work units inside batched launches (from its current tile height).

@@ -24,10 +24,12 @@ namespace {
 using Key = std::tuple<int, int, int, int, int, int, int, uint32_t, bool>;
 std::mutex g_mu;
 std::map<Key, int> g_cache;
-std::map<Key, int> g_cache2;  // two-step kernel
+std::map<Key, int> g_cache2;  // fused kernel
+std::map<Key, int> g_cacheT;  // fused steps per launch chosen by the depth search
 
 Key key_of(const spider_plan_s* p) {
-  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine * 8 + p->split + 64 * p->band_h, p->rowmask,
+  return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine * 8 + p->split + 64 * p->band_h + 4096 * p->row_swap + 8192 * p->time_block,
+             p->rowmask,
              p->has_zero_tap);
 }
 
@@ -63,6 +65,37 @@ static std::vector<int> candidates(int h0, int n) {
   return std::vector<int>(c.begin(), c.end());
 }
 
+// Fastest segment height of the fused kernel at the plan's time_block: *h in/out
+// (the starting height), *ms the time of one launch at the chosen height.
+static hipError_t tune_fused(spider_plan_s* p, void* tmp, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int* h,
+                             float* ms_out) {
+  const int reps = 4;
+  hipError_t e = hipSuccess;
+  int best = *h;
+  float best_ms = 1e30f;
+  const std::vector<int> cand = candidates(*h, p->ny);
+  for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
+    set_tile2(p, cand[i]);
+    if (launch_step2(p, p->d_scratch, tmp, s) != SPIDER_OK) return hipErrorUnknown;  // warm-up
+    e = hipEventRecord(e0, s);
+    for (int r = 0; e == hipSuccess && r < reps; ++r)
+      if (launch_step2(p, (r & 1) ? tmp : p->d_scratch, (r & 1) ? p->d_scratch : tmp, s) != SPIDER_OK)
+        e = hipErrorUnknown;
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = p->tile_h2;
+    }
+  }
+  *h = best;
+  *ms_out = best_ms / reps;
+  set_tile2(p, best);
+  return e;
+}
+
 spider_status autotune_tile(spider_plan_s* p) {
   const Key k = key_of(p);
   {
@@ -71,7 +104,11 @@ spider_status autotune_tile(spider_plan_s* p) {
     if (it != g_cache.end()) {
       set_tile(p, it->second);
       auto it2 = g_cache2.find(k);
-      if (p->time_block == 2 && it2 != g_cache2.end()) set_tile2(p, it2->second);
+      auto itT = g_cacheT.find(k);
+      if (p->tune_depth && itT != g_cacheT.end() && it2 != g_cache2.end())
+        set_time_block(p, itT->second, it2->second);
+      else if (p->time_block >= 2 && it2 != g_cache2.end())
+        set_tile2(p, it2->second);
       return SPIDER_OK;
     }
   }
@@ -107,28 +144,33 @@ spider_status autotune_tile(spider_plan_s* p) {
     }
   }
   set_tile(p, best);
-  // the two-step kernel has its own height
+  // the fused kernel has its own height, and where the plan lets it, the number
+  // of fused steps is chosen too: the fastest time per step over the depths
   int best2 = p->tile_h2;
-  if (e == hipSuccess && p->time_block == 2) {
-    float best2_ms = 1e30f;
-    const std::vector<int> cand2 = candidates(p->tile_h2, p->ny);
-    for (size_t i = 0; e == hipSuccess && i < cand2.size(); ++i) {
-      set_tile2(p, cand2[i]);
-      if (launch_step2(p, p->d_scratch, tmp, s) != SPIDER_OK) break;
-      e = hipEventRecord(e0, s);
-      for (int r = 0; e == hipSuccess && r < reps; ++r)
-        if (launch_step2(p, (r & 1) ? tmp : p->d_scratch, (r & 1) ? p->d_scratch : tmp, s) != SPIDER_OK)
-          e = hipErrorUnknown;
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e == hipSuccess && ms < best2_ms) {
-        best2_ms = ms;
-        best2 = cand2[i];
+  if (e == hipSuccess && p->time_block >= 2) {
+    float ms2 = 1e30f;
+    e = tune_fused(p, tmp, s, e0, e1, &best2, &ms2);
+    if (e == hipSuccess && p->tune_depth) {
+      const int T0 = p->time_block;
+      int bestT = T0, bestT_h = best2;
+      float best_per_step = ms2 / T0;
+      for (int T = 2; e == hipSuccess && T <= p->max_time_block; ++T) {
+        if (T == T0) continue;
+        set_time_block(p, T, 0);
+        int h = p->tile_h2;
+        float ms = 1e30f;
+        e = tune_fused(p, tmp, s, e0, e1, &h, &ms);
+        if (e == hipSuccess && ms / T < best_per_step) {
+          best_per_step = ms / T;
+          bestT = T;
+          bestT_h = h;
+        }
       }
+      set_time_block(p, bestT, bestT_h);
+      best2 = bestT_h;
+    } else {
+      set_tile2(p, best2);
     }
-    set_tile2(p, best2);
   }
   if (s) hipStreamSynchronize(s);
   if (e0) hipEventDestroy(e0);
@@ -139,6 +181,7 @@ spider_status autotune_tile(spider_plan_s* p) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[k] = best;
   g_cache2[k] = best2;
+  g_cacheT[k] = p->time_block;
   return SPIDER_OK;
 }
 

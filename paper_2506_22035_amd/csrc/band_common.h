@@ -83,10 +83,24 @@ struct LineWalk {
   }
 };
 
+// A permuted choice of the chunk that lane `lane` (< 34) stages.  Chunk c lands
+// at dword 10 (c / 2) + 4 (c % 2) of the padded row and is written as two 8-byte
+// stores; with lanes 13..19 taking chunks 14, 16, 18, 13, 15, 17, 19 every 16-lane
+// group of those stores touches each of the 32 banks exactly once (with lane =
+// chunk, chunks 0 / 13 and 2 / 15 share banks).  The 1-D kernel stages this way
+// (about 10 % faster); the 2-D and 3-D kernels measured faster with lane = chunk,
+// whose loads keep consecutive lanes on consecutive chunks.
+__device__ __forceinline__ int staged_chunk(int lane) {
+  if (lane < 13) return lane;
+  if (lane < 16) return 14 + 2 * (lane - 13);
+  if (lane < 20) return 13 + 2 * (lane - 16);
+  return lane;
+}
+
 // Byte offset of this lane's 16-byte chunk within a staged line (strip at x0):
-// chunk c = lane covers x in [x0 - 8 + 8c, x0 + 8c); lanes >= 34 get an
-// offset that is always out of range.  A negative x wraps to a huge unsigned
-// offset, which is out of range as well.
+// chunk c = lane covers x in [x0 - 8 + 8c, x0 + 8c); lanes >= 34 get an offset
+// that is always out of range.  A negative x wraps to a huge unsigned offset,
+// which is out of range as well.
 __device__ __forceinline__ uint32_t chunk_voffset(int x0, int lane) {
   return lane < kRowChunks ? (uint32_t)((x0 - 8 + 8 * lane) * 2) : 0x7ffffff0u;
 }

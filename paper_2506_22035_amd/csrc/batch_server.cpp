@@ -157,6 +157,7 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     const spider_plan_s* p = it.plan;
     if (p->engine == SPIDER_ENGINE_DIRECT || p->carry != p->operand || p->ndim == 1)
       return fail(SPIDER_ERR_UNSUPPORTED, "batched apply runs 2-D/3-D grids on the matrix engines with 16-bit carries");
+    if (p->row_swap) return fail(SPIDER_ERR_UNSUPPORTED, "batched apply runs the implicit row swap only");
     if (p->ndim == 2 ? p->r > 3 : p->r != 1)
       return fail(SPIDER_ERR_UNSUPPORTED, "batched apply supports 2-D radius 1..3 and 3-D radius 1");
     if (operand < 0) {
@@ -452,8 +453,9 @@ spider_status spider_submit(spider_server_t S, spider_plan_t plan, const void* i
   clear_err();
   if (!S || !plan || !in || !out || !ticket || steps < 0) return fail(SPIDER_ERR_INVALID, "bad submit arguments");
   if (plan->engine == SPIDER_ENGINE_DIRECT || plan->carry != plan->operand || plan->ndim == 1 ||
-      (plan->ndim == 2 ? plan->r > 3 : plan->r != 1))
-    return fail(SPIDER_ERR_UNSUPPORTED, "the server runs 16-bit plans: 2-D radius 1..3, 3-D radius 1");
+      (plan->ndim == 2 ? plan->r > 3 : plan->r != 1) || plan->row_swap)
+    return fail(SPIDER_ERR_UNSUPPORTED,
+                "the server runs 16-bit plans with the implicit row swap: 2-D radius 1..3, 3-D radius 1");
   const size_t fp = 2 * plan->grid_bytes;
   if (fp > S->budget) return fail(SPIDER_ERR_OOM, "request needs %zu bytes, budget is %zu", fp, S->budget);
   std::lock_guard<std::mutex> lk(S->mu);

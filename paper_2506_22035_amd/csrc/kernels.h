@@ -34,6 +34,10 @@ hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* grids_d
                          int n, hipStream_t s);
 hipError_t launch_band3d(int r, int operand, int engine, const BandGrid* grids_dev, const BandGrid* grids_host,
                          int n, hipStream_t s);
+// One 2-D step of the 16-point sparse band kernel with the row swap done
+// explicitly (a copy into a swapped operand tile in LDS) instead of in the
+// gather offsets; same result bit for bit (the comparison of Sec. 3.2, Table 3).
+hipError_t launch_band2d_xswap(int r, int operand, const BandGrid& g, hipStream_t s);
 
 // Two fused time steps per launch (2-D, r <= 3).  The grid's strips are
 // kStripW2_host = 240 outputs wide (nstrips = ceil(nx / 240)).
@@ -61,6 +65,20 @@ int band2d_pair_blocks_per_cu(int r, int operand, int engine);
 constexpr int kStripWPair2 = 240;
 hipError_t launch_band2d_pair_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
 int band2d_pair_tb2_blocks_per_cu(int r, int operand, int engine);
+// T = 3 or 4 fused steps on paired-line bands (16-bit carry, r <= 3).  The wave
+// computes 256 columns per pass starting at x_lo - pair_tb_margin(T, r); after T
+// passes the values are exact on [x_lo, x_lo + pair_tb_width(T, r)), which it
+// stores.  The margin is the smallest value >= (T - 1) r that is 4 mod 8 (chunks
+// start at x = 4 mod 8); the width the largest multiple of 8 that keeps
+// (T - 1) r valid columns on the right.
+constexpr int pair_tb_margin(int T, int r) {
+  return ((T - 1) * r <= 4) ? 4 : (((T - 1) * r - 4 + 7) / 8) * 8 + 4;
+}
+constexpr int pair_tb_width(int T, int r) {
+  return ((256 - (T - 1) * r - pair_tb_margin(T, r)) / 8) * 8;
+}
+hipError_t launch_band2d_pair_tbt(int r, int operand, int engine, int T, const BandGrid& g, hipStream_t s);
+int band2d_pair_tbt_blocks_per_cu(int r, int operand, int engine, int T);
 // Paired-line bands on fp32 grids: 16-bit operands split from the fp32 values
 // (x_hi, and x_lo when `xlo`); one step (256-column strips) or two fused steps
 // (`fused`, 240 stored columns per strip).

@@ -31,10 +31,33 @@ namespace spider_impl {
 // Every output line accumulates its kernel rows in the same order (0 .. 2R),
 // whatever the segmentation, so results do not depend on the tile height, on
 // batching or on how many steps a launch fuses.
-template <int R, int OP, int ENG, bool ALIGNED>
+//
+// XSWAP = true is the explicit row swap the implicit one replaces (the
+// comparison of Sec. 3.2 / Table 3): each staged line is first copied, as the
+// natural operand tile X[k][n] = x[x0 + 16n - 8 + k], into an LDS tile whose
+// rows are in the swapped order, and the gather then reads that tile at plain
+// offsets.  The arithmetic, and so the result, is the same bit for bit.
+constexpr int kXTileStride = 20;                 // dwords per column of the swapped tile (16 + 4 pad)
+constexpr int kXTileDw = 16 * kXTileStride;      // one swapped operand tile
+template <int R>
+constexpr int band2d_lines() {
+  return (2 * R + 1 >= 5) ? 2 * R + 1 : 2 * (2 * R + 1);
+}
+template <int R>
+constexpr int band2d_xtile_base() {  // 16-byte aligned, after the staged lines
+  return (band2d_lines<R>() * kLdsRowDw + kLdsSpareDw + 3) & ~3;
+}
+// Swapped K-pair slot of natural window pair kp (0..15): the slot the gather's
+// offsets (band_gather_offsets) give that pair.
+__device__ __forceinline__ int xswap_slot(int kp) {
+  const int hi = kp >> 3, kq = kp & 7, hh = kq >> 1;
+  return 4 * hh + ((kq & 1) == (hh & 1) ? 0 : 2) + hi;
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, bool XSWAP = false>
 __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int RR = 2 * R + 1;
-  constexpr int U = (RR >= 5) ? RR : 2 * RR;  // unroll = prefetch depth, multiple of RR
+  constexpr int U = band2d_lines<R>();  // unroll = prefetch depth, multiple of RR
   const int lane = threadIdx.x;
   const int strip = w % g.nstrips, seg = w / g.nstrips;
   // Chunks start at x = 8 (mod 16) in every 2-D kernel, so a point always sits at
@@ -72,6 +95,13 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
   __builtin_amdgcn_s_waitcnt(0);
   int p1, p2;
   band_gather_offsets(lane, &p1, &p2);
+  // explicit swap: lane (n, h) copies natural window pairs 4h..4h+3 of column n
+  // (contiguous in one padded block) to their swapped slots, and reads slots 4h..4h+3
+  const int xn = lane & 15, xh = lane >> 4;
+  const int xsrc = lds_phys(8 * xn + 4 * xh);
+  const int xd0 = xn * kXTileStride + xswap_slot(4 * xh), xd1 = xn * kXTileStride + xswap_slot(4 * xh + 1);
+  const int xd2 = xn * kXTileStride + xswap_slot(4 * xh + 2), xd3 = xn * kXTileStride + xswap_slot(4 * xh + 3);
+  const int xrd = xn * kXTileStride + 4 * xh;
   const uint32_t lvoff = chunk_voffset(x0, lane);
   const uint32_t ovoff = out_voffset(x0, lane);
   const int lw = chunk_lds_offset(lane, U * kLdsRowDw);  // lanes >= 34: spare area
@@ -98,8 +128,10 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
 
   for (int jb = 0; jb < nin; jb += U) {
     wave_lds_sync();  // previous body's gathers are issued before its LDS rows are reused
+    if (lane < kRowChunks) {  // the 34 chunk lanes; the others hold no data
 #pragma unroll
-    for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+      for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    }
     if (jb > 0) {
 #pragma unroll
       for (int q = 0; q < U; ++q) store_packed<ALIGNED>(lout.next(), ovoff, done[q]);  // output jb - U + q - 2R
@@ -110,7 +142,21 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const uint32_t* lrow = lds + q * kLdsRowDw;
-      const u32x4 b = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+      u32x4 b;
+      if constexpr (XSWAP) {
+        // two tiles alternate; the fence of line q - 1 orders this line's copy
+        // after the gather of line q - 2 from the same tile
+        uint32_t* xt = lds + band2d_xtile_base<R>() + (q & 1) * kXTileDw;
+        const uint32_t v0 = lrow[xsrc], v1 = lrow[xsrc + 1], v2 = lrow[xsrc + 2], v3 = lrow[xsrc + 3];
+        xt[xd0] = v0;
+        xt[xd1] = v1;
+        xt[xd2] = v2;
+        xt[xd3] = v3;
+        wave_lds_sync();
+        b = *reinterpret_cast<const u32x4*>(xt + xrd);
+      } else {
+        b = (u32x4){lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+      }
       // Input row j = jb + q feeds output row i = j - a through kernel row a; its
       // accumulator slot is (j - a) mod RR = (q - a) mod RR because U is a multiple of RR.
 #pragma unroll
@@ -133,14 +179,13 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
 
 
 
-template <int R, int OP, int ENG, bool ALIGNED>
+template <int R, int OP, int ENG, bool ALIGNED, bool XSWAP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && ENG == 1) ? 4 : (R <= 3 ? 3 : 2))))
 void band2d_kernel(BandGrid g) {
-  constexpr int RR = 2 * R + 1;
-  constexpr int U = (RR >= 5) ? RR : 2 * RR;
-  __shared__ uint32_t lds[U * kLdsRowDw + kLdsSpareDw];
+  constexpr int kLds = XSWAP ? band2d_xtile_base<R>() + 2 * kXTileDw : band2d_lines<R>() * kLdsRowDw + kLdsSpareDw;
+  __shared__ __attribute__((aligned(16))) uint32_t lds[kLds];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
-  band2d_body<R, OP, ENG, ALIGNED>(g, w, lds);
+  band2d_body<R, OP, ENG, ALIGNED, XSWAP>(g, w, lds);
 }
 
 // ----------------------------------------------------------------------------- 1-D
@@ -167,10 +212,10 @@ __device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* 
   const __amdgpu_buffer_rsrc_t rin =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * 2, kRsrcWord3);
   const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * 2, kRsrcWord3);
-  // lane c < 34 loads x in [x0 - 8 + 8c, x0 + 8c); blocks advance by 512 bytes
-  const int lx = lane < kRowChunks ? -16 + 8 * lane : 0x3ffffff0;
+  // the lane staging chunk c (staged_chunk) loads x in [x0 - 8 + 8c, x0 + 8c); blocks advance by 512 bytes
+  const int lx = lane < kRowChunks ? -16 + 8 * staged_chunk(lane) : 0x3ffffff0;
   const int ox = -8 + 16 * (lane & 15) + 4 * (lane >> 4);
-  const int lw = chunk_lds_offset(lane, U * kLdsRowDw);
+  const int lw = lane < kRowChunks ? lds_phys(4 * staged_chunk(lane)) : U * kLdsRowDw + 4 * (lane - kRowChunks);
   const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
   auto load_blk = [&](int j) {  // block b0 + j, zero beyond the segment
     const int x = 256 * (b0 + j) + lx;
@@ -184,8 +229,10 @@ __device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* 
   const int nbody = (nb + U - 1) / U;
   for (int jb = 0; jb < nbody * U; jb += U) {
     wave_lds_sync();
+    if (lane < kRowChunks) {  // the 34 chunk lanes; the others hold no data
 #pragma unroll
-    for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+      for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    }
     if (jb > 0) {
 #pragma unroll
       for (int q = 0; q < U; ++q) {
@@ -322,8 +369,10 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
 
   for (int jb = 0; jb < nin; jb += U) {
     wave_lds_sync();
+    if (lane < kRowChunks) {  // the 34 chunk lanes; the others hold no data
 #pragma unroll
-    for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+      for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    }
     if (jb > 0) {
 #pragma unroll
       for (int q = 0; q < U; ++q) store_packed<ALIGNED>(lout.next(), ovoff, done[q]);  // output jb - U + q - 4R - 1
@@ -388,17 +437,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3
 
 // ----------------------------------------------------------------------------- dispatch
 
-template <int OP, int ENG, bool AL>
+template <int OP, int ENG, bool AL, bool XSWAP = false>
 static hipError_t dispatch2d(int r, const BandGrid& g, hipStream_t s) {
   const dim3 grid(g.nblocks), block(64);
   switch (r) {
-    case 1: hipLaunchKernelGGL((band2d_kernel<1, OP, ENG, AL>), grid, block, 0, s, g); break;
-    case 2: hipLaunchKernelGGL((band2d_kernel<2, OP, ENG, AL>), grid, block, 0, s, g); break;
-    case 3: hipLaunchKernelGGL((band2d_kernel<3, OP, ENG, AL>), grid, block, 0, s, g); break;
-    case 4: hipLaunchKernelGGL((band2d_kernel<4, OP, ENG, AL>), grid, block, 0, s, g); break;
-    case 5: hipLaunchKernelGGL((band2d_kernel<5, OP, ENG, AL>), grid, block, 0, s, g); break;
-    case 6: hipLaunchKernelGGL((band2d_kernel<6, OP, ENG, AL>), grid, block, 0, s, g); break;
-    case 7: hipLaunchKernelGGL((band2d_kernel<7, OP, ENG, AL>), grid, block, 0, s, g); break;
+    case 1: hipLaunchKernelGGL((band2d_kernel<1, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band2d_kernel<2, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band2d_kernel<3, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
+    case 4: hipLaunchKernelGGL((band2d_kernel<4, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
+    case 5: hipLaunchKernelGGL((band2d_kernel<5, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
+    case 6: hipLaunchKernelGGL((band2d_kernel<6, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
+    case 7: hipLaunchKernelGGL((band2d_kernel<7, OP, ENG, AL, XSWAP>), grid, block, 0, s, g); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -448,6 +497,13 @@ hipError_t launch_band2d(int r, int operand, int engine, const BandGrid* /*grids
   if (operand == 2 && engine == 2) return al ? dispatch2d<2, 2, true>(r, g, s) : dispatch2d<2, 2, false>(r, g, s);
   if (operand == 3 && engine == 1) return al ? dispatch2d<3, 1, true>(r, g, s) : dispatch2d<3, 1, false>(r, g, s);
   if (operand == 3 && engine == 2) return al ? dispatch2d<3, 2, true>(r, g, s) : dispatch2d<3, 2, false>(r, g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_band2d_xswap(int r, int operand, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2) return al ? dispatch2d<2, 1, true, true>(r, g, s) : dispatch2d<2, 1, false, true>(r, g, s);
+  if (operand == 3) return al ? dispatch2d<3, 1, true, true>(r, g, s) : dispatch2d<3, 1, false, true>(r, g, s);
   return hipErrorInvalidValue;
 }
 
@@ -557,8 +613,10 @@ __device__ __forceinline__ void band3d_body(const BandGrid& g, int w, uint32_t* 
     for (int q = 0; q < RR; ++q) {
       const int pj = pb + q;
       wave_lds_sync();
+      if (lane < kRowChunks) {
 #pragma unroll
-      for (int l = 0; l < NL; ++l) store_chunk_lds(lds, lw + l * lstride, stg[l]);
+        for (int l = 0; l < NL; ++l) store_chunk_lds(lds, lw + l * lstride, stg[l]);
+      }
       if (done_plane >= 0) store_plane(done_plane, done);
       stage();  // plane pj + 1
       wave_lds_sync();
@@ -689,13 +747,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 2 &&
   constexpr int kLds = (7 * kLdsRowDw + kLdsSpareDw) > (8 * kPairRowDw) ? (7 * kLdsRowDw + kLdsSpareDw) : (8 * kPairRowDw);
   __shared__ uint32_t lds[kLds];
   const int total = begin[n];
-  const int b = blockIdx.x;
-  if (b >= total) return;
-  // Workgroups are dealt round-robin over the 8 XCDs (b % 8); give each XCD a
-  // contiguous range of units, so that neighbouring units, which read the same
-  // halo lines, run under one L2.  The map is a bijection of [0, total).
-  const int q = total >> 3, rem = total & 7, x = b & 7;
-  const int unit = x * q + (x < rem ? x : rem) + (b >> 3);
+  if ((int)blockIdx.x >= total) return;
+  const int unit = xcd_remap(blockIdx.x, total);  // neighbouring units under one L2
   // grid owning `unit`: last i with begin[i] <= unit
   int lo = 0, hi = n - 1;
   while (lo < hi) {

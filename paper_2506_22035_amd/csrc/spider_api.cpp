@@ -152,7 +152,8 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
     BandGrid g = p->grid_template;
     g.in = src;
     g.out = dst;
-    e = launch_band2d(p->r, p->operand, p->engine, nullptr, &g, 1, s);
+    e = p->row_swap ? launch_band2d_xswap(p->r, p->operand, g, s)
+                    : launch_band2d(p->r, p->operand, p->engine, nullptr, &g, 1, s);
   } else {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -167,7 +168,8 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   BandGrid g = p->grid_tb2;
   g.in = src;
   g.out = dst;
-  hipError_t e = p->band_h != 8               ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
+  hipError_t e = p->time_block > 2 ? launch_band2d_pair_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+                 : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
                  : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, true, g, s)
                                           : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -205,20 +207,21 @@ void set_tile2(spider_plan_s* p, int h) {
   p->grid_tb2.nblocks = p->grid_tb2.nstrips * p->grid_tb2.nsegs_y;
 }
 
-// Segment height of the two-step kernel: one resident round, at least 32 rows
-// (its halo is 4r lines).
+// Segment height of the fused kernel: one resident round, at least 32 rows
+// (its halo is 2 T r lines).
 static int auto_tile_h_tb2(const spider_plan_s* p) {
   int dev = 0, ncu = 256;
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
+  int per_cu = p->time_block > 2 ? band2d_pair_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->time_block)
+               : p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
                : p->carry == SPIDER_F32 ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, true)
                                         : band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
-  const long long nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;  // 240 columns in both layouts
+  const long long nstrips = p->grid_tb2.nstrips;
   const long long segs = std::max<long long>(1, slots / nstrips);
   long long h = (p->ny + segs - 1) / segs;
   h = std::max<long long>(h, 32);
@@ -226,7 +229,17 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
   return (int)h;
 }
 
-// Enqueue the whole time loop as launches of 1 or 2 steps each: buffers b_0 = in,
+void set_time_block(spider_plan_s* p, int T, int tile_h) {
+  p->time_block = T;
+  if (T < 2) return;
+  p->grid_tb2 = p->grid_template;
+  const int sw = T == 2 ? kStripW2_host : pair_tb_width(T, p->r);
+  p->grid_tb2.nstrips = (p->nx + sw - 1) / sw;
+  set_tile2(p, tile_h ? tile_h : auto_tile_h_tb2(p));
+}
+
+// Enqueue the whole time loop as fused launches of time_block steps, then single
+// steps for the remainder: buffers b_0 = in,
 // b_1 .. b_L (L launches) with b_L = out, alternating between out and the plan's
 // scratch so that the last launch lands in out and `in` is never written (unless
 // in == out).
@@ -239,8 +252,9 @@ spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int ste
     }
     return SPIDER_OK;
   }
-  const int pairs = p->time_block == 2 ? steps / 2 : 0;
-  const int launches = pairs + (steps - 2 * pairs);
+  const int tb = p->time_block;
+  const int pairs = tb >= 2 ? steps / tb : 0;  // fused launches of tb steps, then single steps
+  const int launches = pairs + (steps - tb * pairs);
   const void* src = in;
   // b_k = out if (L - k) is even, else scratch.  With in == out and b_1 == out
   // (L odd), launch 1 would read and write one buffer: copy in to scratch first.
@@ -324,11 +338,17 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   if (matrix && ndim == 3 && radius > 1)
     return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines: 3-D radius 1 only in this build");
   if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
-  if (o.time_block < 0 || o.time_block > 2) return fail(SPIDER_ERR_INVALID, "time_block must be 0, 1 or 2");
+  if (o.time_block < 0 || o.time_block > 4) return fail(SPIDER_ERR_INVALID, "time_block must be 0..4");
   if (o.band_height != 0 && o.band_height != 8 && o.band_height != 16)
     return fail(SPIDER_ERR_INVALID, "band_height must be 0, 8 or 16");
   if (o.band_height == 8 && !(matrix && ndim == 2 && radius <= 3 && shape[1] < (1LL << 28)))
     return fail(SPIDER_ERR_UNSUPPORTED, "band_height 8 (paired-line bands) needs a matrix engine, a 2-D grid and radius <= 3");
+  if (o.row_swap != 0 && o.row_swap != 1) return fail(SPIDER_ERR_INVALID, "row_swap must be 0 or 1");
+  if (o.row_swap == 1 && !(engine == SPIDER_ENGINE_SPARSE && low && ndim == 2 && o.band_height != 8 &&
+                           o.time_block != 2))
+    return fail(SPIDER_ERR_UNSUPPORTED,
+                "row_swap 1 (explicit) needs the sparse engine, a 16-bit carry, a 2-D grid, band height 16 and "
+                "one step per launch");
 
   auto* p = new spider_plan_s();
   p->ndim = ndim;
@@ -343,7 +363,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   p->use_graph = o.use_graph;
   // paired-line bands by default where they apply (fewer instructions per output)
   const bool pair_ok = matrix && ndim == 2 && radius <= 3 && shape[1] < (1LL << 28);
-  p->band_h = (o.band_height == 8 || (o.band_height == 0 && pair_ok)) ? 8 : 16;
+  p->row_swap = o.row_swap;
+  p->band_h = (o.band_height == 8 || (o.band_height == 0 && pair_ok && !o.row_swap)) ? 8 : 16;
   const int kw = 2 * radius + 1;
   const int ncoef = ndim == 1 ? kw : (ndim == 2 ? kw * kw : kw * kw * kw);
   p->coeffs.assign(coeffs, coeffs + ncoef);
@@ -445,13 +466,21 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     g.nblocks = ndim == 1 ? g.nsegs_y : g.nstrips * g.nsegs_y * g.nsegs_z;
     set_batch_geometry(p);
     // two fused steps per launch: 2-D, radius <= 3, 16-bit carry
-    const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair);
-    p->time_block = (o.time_block != 1 && tb2_ok) ? 2 : 1;
-    if (p->time_block == 2) {
-      p->grid_tb2 = g;
-      p->grid_tb2.nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;
-      set_tile2(p, o.tile_h ? o.tile_h : auto_tile_h_tb2(p));
+    const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair) && !p->row_swap;
+    // three or four: paired-line bands with a 16-bit carry (the dense engine
+    // measured slower at four)
+    const bool tbt_ok = tb2_ok && pair && low;
+    p->max_time_block = !tb2_ok ? 1 : !tbt_ok ? 2 : (engine == SPIDER_ENGINE_DENSE ? 3 : 4);
+    int T;
+    if (o.time_block == 0) {
+      // deeper fusion pays on large grids; small ones lack waves to hide its longer pipeline
+      const long long pts = (long long)p->ny * p->nx;
+      T = pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2;
+      p->tune_depth = o.autotune && o.tile_h == 0 && p->max_time_block > 2;
+    } else {
+      T = o.time_block;
     }
+    set_time_block(p, std::min(T, p->max_time_block), o.tile_h);
   }
   if (o.autotune && o.tile_h == 0) {
     spider_status st = ensure_scratch(p);
@@ -543,7 +572,7 @@ spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* ti
   }
   if (scratch_bytes) *scratch_bytes = p->grid_bytes;
   if (time_block) *time_block = p->engine == SPIDER_ENGINE_DIRECT ? 1 : p->time_block;
-  if (tile_h2) *tile_h2 = p->time_block == 2 ? p->tile_h2 : 0;
+  if (tile_h2) *tile_h2 = p->time_block >= 2 ? p->tile_h2 : 0;
   return SPIDER_OK;
 }
 

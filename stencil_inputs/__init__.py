@@ -185,6 +185,15 @@ def workload(name, small=False):
         return dict(name=name, ndim=2, r=3, kind="box", coeffs=w, shape=shape, steps=steps,
                     make_grid=lambda dt=np.float32, s=shape: grid_sinusoids(s, 3, dt),
                     seeds=dict(coeffs=s, grid=3))
+    if name == "box2d7r_10240":
+        # Box-2D7R (r = 7, 225 taps), the stencil of the paper's row-swap comparison
+        # (Table 3); it states no size or recipe there, so the Box-2D49P recipe is used
+        w, s = stable_coeffs_gaussian(2, 7, 0, "box")
+        shape = (300, 520) if small else (10240, 10240)
+        steps = 10 if small else 50
+        return dict(name=name, ndim=2, r=7, kind="box", coeffs=w, shape=shape, steps=steps,
+                    make_grid=lambda dt=np.float32, s=shape: grid_sinusoids(s, 3, dt),
+                    seeds=dict(coeffs=s, grid=3))
     if name == "box3d27p_512":
         w = coeffs_uniform01(3, 1, 4)
         shape = (40, 36, 300) if small else (512, 512, 512)

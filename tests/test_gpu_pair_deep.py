@@ -1,0 +1,148 @@
+"""GPU parity of three and four fused time steps per launch on paired-line bands.
+
+Integer cases use kernels with three taps of +-1 and inputs in {-2..2}, so every
+intermediate step stays an integer below 2^11 and the fused result must equal
+the oracle bit for bit, whatever the summation order: this pins the alignment
+of every intermediate level in rows and columns, the zero halo applied between
+fused steps, the strip margins and the ragged edges.  Float cases are held to
+the stated tolerances and must not depend on the segment height.
+"""
+import numpy as np
+import pytest
+
+import paper_2506_22035_amd as sp
+import stencil_inputs as si
+from gpu_helpers import empty_like_dev, from_dev, rel_errors, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2)}
+SHAPES = [(300, 520), (77, 301), (1, 1), (5, 8), (33, 256), (260, 1030), (2, 130), (41, 128), (64, 233), (19, 700)]
+
+
+def run(plan, x_dev, steps):
+    y = empty_like_dev(x_dev)
+    plan.apply(x_dev, y, steps)
+    return from_dev(y)
+
+
+def sparse_int_taps(r, seed):
+    """Three taps of +-1 at random positions (the centre always among them)."""
+    rng = np.random.default_rng(seed)
+    k = 2 * r + 1
+    w = np.zeros((k, k))
+    w[r, r] = 1.0
+    cells = [(i, j) for i in range(k) for j in range(k) if (i, j) != (r, r)]
+    for idx in rng.choice(len(cells), 2, replace=False):
+        w[cells[idx]] = rng.choice([-1.0, 1.0])
+    return w
+
+
+@pytest.mark.parametrize("T", [3, 4])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_fused_integer_exact(oracle_mod, T, engine, shape):
+    for r in (1, 2, 3):
+        for seed in (1, 2):
+            w = sparse_int_taps(r, 100 * r + seed)
+            x = si.grid_integer(shape, -2, 2, 7 + shape[0] + seed)
+            xd, x64 = to_dev(x, "f16")
+            plan = sp.Plan(w, shape, carry="f16", engine=engine, band_height=8, time_block=T)
+            info = plan.info()
+            # the dense engine fuses at most three steps (it measured slower at four)
+            assert info["time_block"] == min(T, 3 if engine == "dense" else 4) and info["tile_h2"] % 2 == 0
+            got = run(plan, xd, T)
+            ref = oracle_mod.apply(w, x64, T)
+            assert np.abs(ref).max() < 2048
+            assert np.array_equal(got, ref), (r, seed, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("T", [3, 4])
+@pytest.mark.parametrize("steps", [1, 5, 7, 9])
+def test_steps_not_multiple_of_T(oracle_mod, T, steps):
+    # n steps run n // T fused launches and then n % T single steps
+    shape = (131, 300)
+    w = sparse_int_taps(2, 9)
+    x = si.grid_integer(shape, -1, 1, 11)
+    xd, x64 = to_dev(x, "f16")
+    ref = oracle_mod.apply(w, x64, steps)
+    if np.abs(ref).max() >= 2048:
+        pytest.skip("values leave the exact fp16 range")
+    plan = sp.Plan(w, shape, carry="f16", band_height=8, time_block=T)
+    assert np.array_equal(run(plan, xd, steps), ref)
+
+
+@pytest.mark.parametrize("T", [3, 4])
+@pytest.mark.parametrize("carry", ["f16", "bf16"])
+@pytest.mark.parametrize("name", ["box2d49p_10240", "star2d13p_8192"])
+def test_fused_tolerance(oracle_mod, T, carry, name):
+    wl = si.workload(name, small=True)
+    xd, x64 = to_dev(wl["make_grid"](), carry)
+    ref = oracle_mod.apply(wl["coeffs"], x64, wl["steps"])
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, band_height=8, time_block=T)
+    got = run(plan, xd, wl["steps"])
+    rms, mx = rel_errors(got, ref)
+    print("%s %s T=%d: rel-RMS %.3e rel-max %.3e" % (name, carry, T, rms, mx))
+    assert rms <= TOL[carry][0] and mx <= TOL[carry][1]
+    single = run(sp.Plan(wl["coeffs"], wl["shape"], carry=carry, band_height=8, time_block=1), xd, wl["steps"])
+    rms1, _ = rel_errors(got, single)
+    assert rms1 <= TOL[carry][0]
+
+
+@pytest.mark.parametrize("T", [3, 4])
+def test_even_radius_identical_to_single_steps(T):
+    # with even r every intermediate level starts on an even row, as single steps do
+    rng = np.random.default_rng(31)
+    w = rng.uniform(0, 1, (5, 5))
+    w /= w.sum()
+    shape = (203, 517)
+    xd, _ = to_dev(rng.uniform(0, 1, shape), "f16")
+    a = run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=T), xd, 2 * T)
+    b = run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=1), xd, 2 * T)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("T", [3, 4])
+def test_fused_tile_heights_agree_and_aliasing(T):
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    res = []
+    for th in (0, 2, 8, 31, 64, 301, 1000):
+        plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", band_height=8, tile_h=th, time_block=T)
+        res.append(run(plan, xd, 2 * T))
+    for r_ in res[1:]:
+        assert np.array_equal(r_, res[0])
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", band_height=8, time_block=T)
+    keep = xd.clone()
+    for steps in (T, T + 1, 2 * T):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), run(plan, xd, steps))
+    assert torch.equal(xd, keep)
+
+
+def test_unsupported_depths_fall_back():
+    # 3 or 4 need paired-line bands and a 16-bit carry; otherwise two where supported, else one
+    w = np.ones((3, 3)) / 9
+    assert sp.Plan(w, (64, 64), carry="f16", band_height=16, time_block=4).info()["time_block"] == 2
+    assert sp.Plan(w, (64, 64), carry="f32", engine="sparse", split=3, time_block=3).info()["time_block"] == 2
+    w4 = np.ones((9, 9)) / 81
+    assert sp.Plan(w4, (64, 64), carry="f16", time_block=4).info()["time_block"] == 1
+
+
+@pytest.mark.parametrize("T", [3, 4])
+def test_full_size_box2d49p_sampled(oracle_mod, T):
+    from test_gpu_parity import _cone_samples
+    wl = si.workload("box2d49p_10240")
+    xd, x64 = to_dev(wl["make_grid"](), "f16")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", band_height=8, time_block=T)
+    got = run(plan, xd, wl["steps"])
+    rng = np.random.default_rng(5)
+    n = wl["shape"][0]
+    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (3, 231), (5, 232), (7, 233), (n // 2, 464)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(8)]
+    ref = _cone_samples(oracle_mod, wl["coeffs"], x64, wl["steps"], pts)
+    rms, mx = rel_errors(np.array([got[p] for p in pts]), ref)
+    print("full-size T=%d sampled rel-RMS %.3e rel-max %.3e" % (T, rms, mx))
+    assert rms <= TOL["f16"][0] and mx <= TOL["f16"][1]

@@ -378,6 +378,14 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.spider_plan(w4.ctypes.data, 2, shp, 4, ctypes.byref(o), ctypes.byref(h)) == 2
     o = opts(band_height=8, carry=1, engine=3)  # and a matrix engine
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2
+    o = opts(row_swap=2)
+    assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    # the explicit row swap: sparse engine, 16-bit carry, 2-D, band height 16, one step per launch
+    for kw in (dict(engine=2), dict(band_height=8), dict(time_block=2), dict(carry=1, engine=1, split=3)):
+        o = opts(row_swap=1, **kw)
+        assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2, kw
+    o = opts(row_swap=1)
+    assert L.spider_plan(w3.ctypes.data, 3, shp3, 1, ctypes.byref(o), ctypes.byref(h)) == 2
     assert L.spider_apply(None, None, None, 1, None) == 1
     assert L.spider_plan_destroy(None) == 0
     with pytest.raises(sp.SpiderError):
