@@ -78,10 +78,13 @@ typedef struct {
                        radius <= 3 on the matrix engines with a 16-bit carry or with
                        paired-line bands, else one),
                        1 = one step per launch, 2 = two where supported, 3 or 4 = that many
-                       for paired-line bands with a 16-bit carry (else two where
-                       supported, else one).  A time loop of n steps runs n / T fused
-                       launches and then n mod T single steps.  The results agree to
-                       rounding; see band_height for when they are identical. */
+                       for paired-line bands with a 16-bit carry and for 1-D lines with
+                       a 16-bit carry and radius <= 3 (else two where supported, else
+                       one).  With 0 and autotune the plan also times the depths and
+                       keeps the fastest per step.  A time loop of n steps runs n / T
+                       fused launches and then n mod T single steps.  The results agree
+                       to rounding; on 1-D lines they are identical bit for bit, and see
+                       band_height for 2-D. */
     int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16
                       (default, also when 0) or SPIDER_BF16.  With a 16-bit carry the operand
                       is the carry type and this field must be 0 or equal to it. */

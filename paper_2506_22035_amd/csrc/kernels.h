@@ -90,6 +90,9 @@ int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, bool
 // outputs at x0 = 256 j - 8; each wave streams seg_h consecutive blocks (nblocks =
 // ceil(nstrips / seg_h)).  One packed kernel row.
 hipError_t launch_band1d(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
+// T = 2..4 fused steps on the 1-D band engine (r <= 3): seg_h output blocks per
+// wave, each wave also computing T - 1 blocks on either side for its neighbours.
+hipError_t launch_band1d_tbt(int r, int operand, int engine, int T, const BandGrid& g, hipStream_t s);
 
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);

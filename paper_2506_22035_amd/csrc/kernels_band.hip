@@ -294,6 +294,160 @@ hipError_t launch_band1d(int r, int operand, int engine, const BandGrid& g, hipS
   return hipErrorInvalidValue;
 }
 
+// ----------------------------------------------------------------------------- 1-D, T fused steps
+// T = 2..4 time steps per launch.  Level t (0 = input, T = output) of block k
+// covers x in [256 k - 8, 256 k + 248), and its staged row for the next level
+// is x in [256 k - 16, 256 k + 256): the block's 256 values with the last 8 of
+// block k - 1 in front and the first 8 of block k + 1 behind.  At stream
+// iteration i level t computes block s0 + i - 2 (t - 1), so every level reads
+// only rows written in earlier iterations; a finished block writes its values
+// into its own row, its first 8 into the tail of the previous row and its last
+// 8 into the head of the next, in a ring of four rows per intermediate level.
+// Each value is summed exactly as in a single step, so the fused result equals
+// T single steps bit for bit.  A wave owning output blocks [b0, b0 + nb)
+// starts at input block s0 = b0 - (T - 1); the extra blocks at both ends are
+// computed for their neighbours and not stored.
+template <int R, int OP, int ENG, bool ALIGNED, int T>
+__device__ __forceinline__ void band1d_tbt_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int U = 8;  // input blocks staged per body (a multiple of the ring size 4)
+  const int lane = threadIdx.x;
+  const int nblk_total = g.nstrips;
+  const int b0 = w * g.seg_h;
+  const int nb = min(g.seg_h, nblk_total - b0);
+  const int s0 = b0 - (T - 1);
+  const int nin = nb + 2 * (T - 1);       // input blocks level 1 needs
+  const int nit = nb + 3 * (T - 1);       // iterations until the last output block
+  const int nx = g.nx;
+  const u32x4 A0 = (ENG == 1) ? reinterpret_cast<const u32x4*>(g.apack)[lane] : (u32x4){0, 0, 0, 0};
+  const u32x4 Dh = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 0];
+  const u32x4 Dl = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 1];
+  const uint32_t I0 = (ENG == 1) ? g.ipack[lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const __amdgpu_buffer_rsrc_t rin =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * 2, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * 2, kRsrcWord3);
+  const int lx = lane < kRowChunks ? -16 + 8 * staged_chunk(lane) : 0x3ffffff0;
+  const int lw = lane < kRowChunks ? lds_phys(4 * staged_chunk(lane)) : U * kLdsRowDw + 4 * (lane - kRowChunks);
+  const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
+  // this lane's 4 outputs of a block: x = 256 k + ox + e, row position 8 + 16n + 4h
+  const int n = lane & 15, h = lane >> 4;
+  const int ox = -8 + 16 * n + 4 * h;
+  const int wmain = lds_phys(4 + 8 * n + 2 * h);
+  const bool head = n == 0 && h < 2, tail = n == 15 && h >= 2;  // first / last 8 values of the block
+  const int whead = lds_phys(132 + 2 * h), wtail = lds_phys(2 * (h - 2));
+  uint32_t* ring = lds + U * kLdsRowDw + kLdsSpareDw;  // (T - 1) levels x 4 rows
+  for (int i = lane; i < (T - 1) * 4 * kLdsRowDw; i += 64) ring[i] = 0u;
+
+  auto load_blk = [&](int it) {  // input block s0 + it, zero where level 1 does not need it
+    const int x = 256 * (s0 + it) + lx;
+    const uint32_t off = (it < nin && lane < kRowChunks) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    return load_chunk<ALIGNED>(rin, off);
+  };
+  u32x4 stg[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) stg[q] = load_blk(q);
+  uint2 done[U];
+  const int nbody = (nit + U - 1) / U;
+  for (int jb = 0; jb < nbody * U; jb += U) {
+    wave_lds_sync();
+    if (lane < kRowChunks) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) store_chunk_lds(lds, lw + q * lstride, stg[q]);
+    }
+    if (jb > 0) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int k = s0 + (jb - U + q) - 2 * (T - 1);  // output block of that iteration
+        const int x = 256 * k + ox;
+        const uint32_t off = (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+        store_packed<ALIGNED>(rout, off, done[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) stg[q] = load_blk(jb + U + q);
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int it = jb + q;
+      wave_lds_sync();  // rows written by the previous iteration are visible
+      f32x4 acc[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        // level t + 1 of block s0 + it - 2t reads the level-t row (input row q for t = 0)
+        const uint32_t* row = (t == 0) ? lds + q * kLdsRowDw
+                                       : ring + ((t - 1) * 4 + ((q - 2 * t) & 3)) * kLdsRowDw;
+        const u32x4 b = {row[p1], row[p1 + 10], row[p2], row[p2 + 10]};
+        acc[t] = band_mma<OP, ENG, 0>((f32x4){0.f, 0.f, 0.f, 0.f}, A0, Dh, Dl, I0, b);
+      }
+      done[q] = pack_out<OP>(acc[T - 1]);
+#pragma unroll
+      for (int t = 0; t + 1 < T; ++t) {
+        // level t + 1 of block k: zero outside the line, then into its row, the previous
+        // row's tail and the next row's head (ring slots by iteration, U is a multiple of 4)
+        const int k = s0 + it - 2 * t;
+        const int x = 256 * k + ox;
+        uint2 v = pack_out<OP>(acc[t]);
+        uint32_t m0 = 0, m1 = 0;
+        if (x >= 0 && x < nx) m0 |= 0x0000ffffu;
+        if (x + 1 >= 0 && x + 1 < nx) m0 |= 0xffff0000u;
+        if (x + 2 >= 0 && x + 2 < nx) m1 |= 0x0000ffffu;
+        if (x + 3 >= 0 && x + 3 < nx) m1 |= 0xffff0000u;
+        v.x &= m0;
+        v.y &= m1;
+        uint32_t* lev = ring + t * 4 * kLdsRowDw;
+        const int rho = q - 2 * t;
+        *reinterpret_cast<uint2*>(lev + (rho & 3) * kLdsRowDw + wmain) = v;
+        if (head) *reinterpret_cast<uint2*>(lev + ((rho - 1) & 3) * kLdsRowDw + whead) = v;
+        if (tail) *reinterpret_cast<uint2*>(lev + ((rho + 1) & 3) * kLdsRowDw + wtail) = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) {
+    const int k = s0 + (nbody * U - U + q) - 2 * (T - 1);
+    const int x = 256 * k + ox;
+    const uint32_t off = (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    store_packed<ALIGNED>(rout, off, done[q]);
+  }
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, int T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ALIGNED ? 3 : 2))) void band1d_tbt_kernel(BandGrid g) {
+  __shared__ uint32_t lds[8 * kLdsRowDw + kLdsSpareDw + (T - 1) * 4 * kLdsRowDw];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band1d_tbt_body<R, OP, ENG, ALIGNED, T>(g, w, lds);
+}
+
+template <int OP, int ENG, bool AL, int T>
+static hipError_t dispatch1d_tbt(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  switch (r) {
+    case 1: hipLaunchKernelGGL((band1d_tbt_kernel<1, OP, ENG, AL, T>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band1d_tbt_kernel<2, OP, ENG, AL, T>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band1d_tbt_kernel<3, OP, ENG, AL, T>), grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int OP, int ENG, bool AL>
+static hipError_t dispatch1d_tbt_t(int r, int T, const BandGrid& g, hipStream_t s) {
+  if (T == 2) return dispatch1d_tbt<OP, ENG, AL, 2>(r, g, s);
+  if (T == 3) return dispatch1d_tbt<OP, ENG, AL, 3>(r, g, s);
+  if (T == 4) return dispatch1d_tbt<OP, ENG, AL, 4>(r, g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_band1d_tbt(int r, int operand, int engine, int T, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2 && engine == 1) return al ? dispatch1d_tbt_t<2, 1, true>(r, T, g, s) : dispatch1d_tbt_t<2, 1, false>(r, T, g, s);
+  if (operand == 2 && engine == 2) return al ? dispatch1d_tbt_t<2, 2, true>(r, T, g, s) : dispatch1d_tbt_t<2, 2, false>(r, T, g, s);
+  if (operand == 3 && engine == 1) return al ? dispatch1d_tbt_t<3, 1, true>(r, T, g, s) : dispatch1d_tbt_t<3, 1, false>(r, T, g, s);
+  if (operand == 3 && engine == 2) return al ? dispatch1d_tbt_t<3, 2, true>(r, T, g, s) : dispatch1d_tbt_t<3, 2, false>(r, T, g, s);
+  return hipErrorInvalidValue;
+}
+
 // ----------------------------------------------------------------------------- 2-D, two fused steps
 // Temporal blocking (two time steps per launch).  The wave's first pass is the
 // single-step pass on 16 chunks starting 8 columns left of the stored strip

@@ -168,7 +168,8 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   BandGrid g = p->grid_tb2;
   g.in = src;
   g.out = dst;
-  hipError_t e = p->time_block > 2 ? launch_band2d_pair_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+  hipError_t e = p->ndim == 1 ? launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+                 : p->time_block > 2 ? launch_band2d_pair_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
                  : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
                  : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, true, g, s)
                                           : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
@@ -200,6 +201,13 @@ void set_batch_geometry(spider_plan_s* p) {
 }
 
 void set_tile2(spider_plan_s* p, int h) {
+  if (p->ndim == 1) {  // output blocks per wave
+    p->tile_h2 = h;
+    p->grid_tb2.seg_h = h;
+    p->grid_tb2.nsegs_y = (p->grid_tb2.nstrips + h - 1) / h;
+    p->grid_tb2.nblocks = p->grid_tb2.nsegs_y;
+    return;
+  }
   if (p->band_h == 8) h += h & 1;  // paired-line bands: segments start on even rows
   p->tile_h2 = h;
   p->grid_tb2.seg_h = h;
@@ -214,6 +222,13 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
   if (hipGetDevice(&dev) == hipSuccess) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+  }
+  if (p->ndim == 1) {
+    // at least 16 output blocks per wave (each wave also computes 2 (T - 1) extra
+    // blocks), and up to about 12 waves per CU
+    const long long nblk = p->grid_template.nstrips;
+    const long long h = (nblk + 12LL * ncu - 1) / (12LL * ncu);
+    return (int)std::min<long long>(std::max<long long>(h, 16), nblk);
   }
   int per_cu = p->time_block > 2 ? band2d_pair_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->time_block)
                : p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
@@ -233,8 +248,10 @@ void set_time_block(spider_plan_s* p, int T, int tile_h) {
   p->time_block = T;
   if (T < 2) return;
   p->grid_tb2 = p->grid_template;
-  const int sw = T == 2 ? kStripW2_host : pair_tb_width(T, p->r);
-  p->grid_tb2.nstrips = (p->nx + sw - 1) / sw;
+  if (p->ndim != 1) {
+    const int sw = T == 2 ? kStripW2_host : pair_tb_width(T, p->r);
+    p->grid_tb2.nstrips = (p->nx + sw - 1) / sw;
+  }
   set_tile2(p, tile_h ? tile_h : auto_tile_h_tb2(p));
 }
 
@@ -470,12 +487,14 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     // three or four: paired-line bands with a 16-bit carry (the dense engine
     // measured slower at four)
     const bool tbt_ok = tb2_ok && pair && low;
-    p->max_time_block = !tb2_ok ? 1 : !tbt_ok ? 2 : (engine == SPIDER_ENGINE_DENSE ? 3 : 4);
+    // 1-D lines: two to four steps on the 16-point band engine (16-bit carry, r <= 3)
+    const bool tb1_ok = ndim == 1 && radius <= 3 && low && !p->row_swap;
+    p->max_time_block = tb1_ok ? 4 : !tb2_ok ? 1 : !tbt_ok ? 2 : (engine == SPIDER_ENGINE_DENSE ? 3 : 4);
     int T;
     if (o.time_block == 0) {
       // deeper fusion pays on large grids; small ones lack waves to hide its longer pipeline
       const long long pts = (long long)p->ny * p->nx;
-      T = pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2;
+      T = ndim == 1 ? (pts >= (1LL << 22) ? 4 : 2) : pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2;
       p->tune_depth = o.autotune && o.tile_h == 0 && p->max_time_block > 2;
     } else {
       T = o.time_block;

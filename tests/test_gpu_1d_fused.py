@@ -1,0 +1,90 @@
+"""GPU parity of fused time steps on 1-D lines (two to four steps per launch).
+
+A fused launch sums every value exactly as a single step does, so it must equal
+single steps bit for bit on any data, and the oracle bit for bit on integer data
+whose every step stays below 2^11 (three taps of +-1, inputs in {-2..2}).  The
+cases cover lines shorter than a block, ragged ends, segments of one block, step
+counts that T does not divide and in-place applies.
+"""
+import numpy as np
+import pytest
+
+import paper_2506_22035_amd as sp
+import stencil_inputs as si
+from gpu_helpers import empty_like_dev, from_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+LENGTHS = [1, 7, 255, 256, 257, 520, 4096, 10001, 50000, 123457]
+
+
+def run(plan, x_dev, steps):
+    y = empty_like_dev(x_dev)
+    plan.apply(x_dev, y, steps)
+    return from_dev(y)
+
+
+def sparse_int_taps_1d(r, seed):
+    rng = np.random.default_rng(seed)
+    w = np.zeros(2 * r + 1)
+    w[r] = 1.0
+    for i in rng.choice([i for i in range(2 * r + 1) if i != r], 2, replace=False):
+        w[i] = rng.choice([-1.0, 1.0])
+    return w
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_fused_integer_exact(oracle_mod, T, engine, n):
+    for r in (1, 2, 3):
+        w = sparse_int_taps_1d(r, 10 * r + T)
+        xd, x64 = to_dev(si.grid_integer((n,), -2, 2, 3 + n % 101), "f16")
+        plan = sp.Plan(w, (n,), carry="f16", engine=engine, time_block=T)
+        assert plan.info()["time_block"] == T
+        ref = oracle_mod.apply(w, x64, T)
+        assert np.abs(ref).max() < 2048
+        got = run(plan, xd, T)
+        assert np.array_equal(got, ref), (r, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+@pytest.mark.parametrize("carry", ["f16", "bf16"])
+def test_fused_equals_single_steps(T, carry):
+    wl = si.workload("1d5p_10240000", small=True)
+    xd, _ = to_dev(wl["make_grid"](), carry)
+    ref = run(sp.Plan(wl["coeffs"], wl["shape"], carry=carry, time_block=1), xd, 11)
+    for th in (0, 1, 2, 5, 16, 1000):
+        plan = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, time_block=T, tile_h=th)
+        assert np.array_equal(run(plan, xd, 11), ref), th
+
+
+@pytest.mark.parametrize("T", [2, 4])
+def test_fused_aliasing(T):
+    import torch
+    wl = si.workload("1d3p_10240000", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", time_block=T)
+    keep = xd.clone()
+    for steps in (T, T + 1, 3 * T):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), run(plan, xd, steps))
+    assert torch.equal(xd, keep)
+
+
+def test_depth_limits():
+    w = np.array([0.25, 0.5, 0.25])
+    assert sp.Plan(w, (4096,), carry="f16", time_block=4).info()["time_block"] == 4
+    w4 = np.ones(9) / 9
+    assert sp.Plan(w4, (4096,), carry="f16", time_block=4).info()["time_block"] == 1  # r > 3
+    assert sp.Plan(w, (4096,), carry="f32", time_block=4).info()["time_block"] == 1  # direct engine
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+def test_full_size_equals_single_steps(T):
+    wl = si.workload("1d3p_10240000")
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    a = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f16", time_block=T), xd, 12)
+    b = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f16", time_block=1), xd, 12)
+    assert np.array_equal(a, b)
