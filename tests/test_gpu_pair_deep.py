@@ -146,3 +146,18 @@ def test_full_size_box2d49p_sampled(oracle_mod, T):
     rms, mx = rel_errors(np.array([got[p] for p in pts]), ref)
     print("full-size T=%d sampled rel-RMS %.3e rel-max %.3e" % (T, rms, mx))
     assert rms <= TOL["f16"][0] and mx <= TOL["f16"][1]
+
+
+def test_autotuned_depth(oracle_mod):
+    # time_block 0 with autotuning: the plan times depths 2..4 and keeps one
+    wl = si.workload("star2d13p_8192", small=True)
+    xd, x64 = to_dev(wl["make_grid"](), "f16")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True)
+    info = plan.info()
+    assert 2 <= info["time_block"] <= 4 and info["tile_h2"] % 2 == 0
+    got = run(plan, xd, wl["steps"])
+    rms, mx = rel_errors(got, oracle_mod.apply(wl["coeffs"], x64, wl["steps"]))
+    assert rms <= TOL["f16"][0] and mx <= TOL["f16"][1]
+    # a second plan of the same shape reuses the cached choice
+    again = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True).info()
+    assert (again["time_block"], again["tile_h2"]) == (info["time_block"], info["tile_h2"])
