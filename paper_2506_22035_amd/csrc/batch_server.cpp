@@ -171,7 +171,12 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
   }
   // the kernel variant holding only the body classes present (2-D: 1, 3-D: 2)
   int cls = 0;
-  for (const auto& it : items) cls |= it.plan->ndim == 3 ? 2 : 1;
+  bool aligned = true;
+  for (const auto& it : items) {
+    cls |= it.plan->ndim == 3 ? 2 : 1;
+    aligned = aligned && it.plan->nx % 8 == 0;
+  }
+  if (aligned) cls |= 4;  // aligned bodies only
   // Per item: the first source, after the in == out copy when needed.
   std::vector<const void*> src(n);
   for (int i = 0; i < n; ++i) {

@@ -111,7 +111,8 @@ enum BatchKind : int {
 //   begin    device array of n+1 prefix sums of grids[i].nblocks
 //   units    begin[n] (host copy): one workgroup per work unit
 // cls: bodies compiled into the launched kernel, 1 = 2-D kinds only, 2 = 3-D kinds
-// only, 3 = both (a batch of one class gets a smaller register budget per wave).
+// only, 3 = both (a batch of one class gets a smaller register budget per wave);
+// + 4 when every grid's row length is a multiple of 8 (aligned bodies only).
 hipError_t launch_band_batch(int operand, int engine, int cls, const BandGrid* grids, const int* kinds,
                              const int* begin, int n, int units, hipStream_t s);
 

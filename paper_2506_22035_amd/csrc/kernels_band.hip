@@ -180,7 +180,9 @@ __device__ __forceinline__ void band2d_body(const BandGrid& g, int w, uint32_t* 
 
 
 template <int R, int OP, int ENG, bool ALIGNED, bool XSWAP = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && ENG == 1) ? 4 : (R <= 3 ? 3 : 2))))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(
+    ENG == 1 ? ((R <= 2 && ALIGNED && !XSWAP) ? 4 : ((R <= 2 || (R == 3 && ALIGNED)) ? 3 : 2))
+             : (R <= 2 ? 3 : (R <= 4 ? 2 : 1)))))
 void band2d_kernel(BandGrid g) {
   constexpr int kLds = XSWAP ? band2d_xtile_base<R>() + 2 * kXTileDw : band2d_lines<R>() * kLdsRowDw + kLdsSpareDw;
   __shared__ __attribute__((aligned(16))) uint32_t lds[kLds];
@@ -263,7 +265,7 @@ __device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* 
 }
 
 template <int R, int OP, int ENG, bool ALIGNED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void band1d_kernel(BandGrid g) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ALIGNED ? 4 : 3))) void band1d_kernel(BandGrid g) {
   __shared__ uint32_t lds[8 * kLdsRowDw + kLdsSpareDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
   band1d_body<R, OP, ENG, ALIGNED>(g, w, lds);
@@ -580,7 +582,7 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
 }
 
 template <int R, int OP, int ENG, bool ALIGNED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3 : 2))) void band2d_tb2_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 && R <= 2) ? 3 : 2))) void band2d_tb2_kernel(
     BandGrid g) {
   constexpr int RR = 2 * R + 1;
   constexpr int U = (RR >= 5) ? RR : 2 * RR;
@@ -808,7 +810,7 @@ __device__ __forceinline__ void band3d_body(const BandGrid& g, int w, uint32_t* 
 }
 
 template <int R, int OP, int ENG, bool ALIGNED, uint32_t MASK>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3 : 2))) void band3d_kernel(BandGrid g) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 && ALIGNED) ? 3 : 2))) void band3d_kernel(BandGrid g) {
   constexpr int NL = kRowsY3 + 2 * R;
   __shared__ uint32_t lds[NL * kLdsRowDw + kLdsSpareDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -895,9 +897,11 @@ int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned) {
 // exactly begin[n] workgroups.  CLS selects the bodies compiled in: 1 = 2-D
 // kinds, 2 = 3-D kinds, 3 = all.
 template <int OP, int ENG, int CLS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 2 && ENG == 1) ? 3 : 2))) void band_batch_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 6 && ENG == 1) ? 3 : 2))) void band_batch_kernel(
     const BandGrid* __restrict__ grids, const int* __restrict__ kinds, const int* __restrict__ begin, int n) {
-  constexpr bool k2d = (CLS & 1) != 0, k3d = (CLS & 2) != 0;
+  // CLS bit 4: every grid's row length is a multiple of 8, so only the aligned
+  // bodies are compiled in (the unaligned ones need more registers)
+  constexpr bool k2d = (CLS & 1) != 0, k3d = (CLS & 2) != 0, al_only = (CLS & 4) != 0;
   constexpr int kLds = (7 * kLdsRowDw + kLdsSpareDw) > (8 * kPairRowDw) ? (7 * kLdsRowDw + kLdsSpareDw) : (8 * kPairRowDw);
   __shared__ uint32_t lds[kLds];
   const int total = begin[n];
@@ -912,7 +916,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 2 &&
   }
   const BandGrid g = grids[lo];
   const int w = unit - begin[lo];
-  const bool al = (g.nx % 8) == 0;
+  const bool al = al_only || (g.nx % 8) == 0;
   const int kind = kinds[lo];
   if constexpr (k2d) {
     switch (kind) {
@@ -947,18 +951,21 @@ template <int OP, int ENG>
 static hipError_t launch_batch_cls(int cls, const BandGrid* grids, const int* kinds, const int* begin, int n,
                                    int units, hipStream_t s) {
   const dim3 grid(units), block(64);
-  if (cls == 1)
-    hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 1>), grid, block, 0, s, grids, kinds, begin, n);
-  else if (cls == 2)
-    hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 2>), grid, block, 0, s, grids, kinds, begin, n);
-  else
-    hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 3>), grid, block, 0, s, grids, kinds, begin, n);
+  switch (cls) {
+    case 1: hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 1>), grid, block, 0, s, grids, kinds, begin, n); break;
+    case 2: hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 2>), grid, block, 0, s, grids, kinds, begin, n); break;
+    case 3: hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 3>), grid, block, 0, s, grids, kinds, begin, n); break;
+    case 5: hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 5>), grid, block, 0, s, grids, kinds, begin, n); break;
+    case 6: hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 6>), grid, block, 0, s, grids, kinds, begin, n); break;
+    case 7: hipLaunchKernelGGL((band_batch_kernel<OP, ENG, 7>), grid, block, 0, s, grids, kinds, begin, n); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_band_batch(int operand, int engine, int cls, const BandGrid* grids, const int* kinds,
                              const int* begin, int n, int units, hipStream_t s) {
-  if (cls < 1 || cls > 3 || units < 1) return hipErrorInvalidValue;
+  if (cls < 1 || cls > 7 || cls == 4 || units < 1) return hipErrorInvalidValue;
   if (operand == 2 && engine == 1) return launch_batch_cls<2, 1>(cls, grids, kinds, begin, n, units, s);
   if (operand == 2 && engine == 2) return launch_batch_cls<2, 2>(cls, grids, kinds, begin, n, units, s);
   if (operand == 3 && engine == 1) return launch_batch_cls<3, 1>(cls, grids, kinds, begin, n, units, s);

@@ -197,7 +197,7 @@ __device__ __forceinline__ void band2d_f32_body(const BandGrid& g, int w, uint32
 }
 
 template <int R, int OP, int ENG, bool ALIGNED, bool XLO>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && ENG == 1) ? 3 : 2))) void band2d_f32_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && ENG == 1 && ALIGNED) ? 3 : (R <= 5 ? 2 : 1)))) void band2d_f32_kernel(
     BandGrid g) {
   constexpr int RR = 2 * R + 1;
   constexpr int U = (RR >= 5) ? RR : 2 * RR;

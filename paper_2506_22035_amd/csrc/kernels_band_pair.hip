@@ -25,7 +25,7 @@
 namespace spider_impl {
 
 template <int R, int OP, int ENG, bool ALIGNED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void band2d_pair_kernel(BandGrid g) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ALIGNED ? 4 : (ENG == 1 ? 3 : 2)))) void band2d_pair_kernel(BandGrid g) {
   constexpr int NP = R + 1;
   constexpr int UP = (NP >= 3) ? NP : 2 * NP;
   __shared__ uint32_t lds[2 * UP * kPairRowDw];
@@ -46,7 +46,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void ba
 // odd rows, unlike the one-step kernel's output pairs, so the fused result
 // agrees with two single steps to rounding, not bit for bit; it never depends
 // on the tiling.
-template <int R, int OP, int ENG, bool ALIGNED>
+// EDGE = false: every row and column the wave computes lies inside the grid, so
+// the intermediate values need no zero-halo masking.
+template <int R, int OP, int ENG, bool ALIGNED, bool EDGE>
 __device__ __forceinline__ void band2d_pair_tb2_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int NP = R + 1;
   constexpr int UP = (NP >= 3) ? NP : 2 * NP;
@@ -194,12 +196,18 @@ __device__ __forceinline__ void band2d_pair_tb2_body(const BandGrid& g, int w, u
       done_b[q] = pack_out<OP>(b2[fs]);
       a2[fs] = b2[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
       // intermediate pair P - R is complete: round, zero outside the grid, keep for the next iteration
-      const int mrow = mrow0 + 2 * (P - R);
-      const bool rok = mrow >= 0 && mrow < ny;
       const uint2 va = pack_out<OP>(a1[fs]), vb = pack_out<OP>(b1[fs]);
       uint32_t* mc = mid + (P & 1) * 2 * kPairRowDw;
-      *reinterpret_cast<uint2*>(mc + mw) = make_uint2(rok ? (va.x & ma0) : 0u, rok ? (va.y & ma1) : 0u);
-      *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) = make_uint2(rok ? (vb.x & mb0) : 0u, rok ? (vb.y & mb1) : 0u);
+      if constexpr (!EDGE) {
+        *reinterpret_cast<uint2*>(mc + mw) = va;
+        *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) = vb;
+      } else {
+        const int mrow = mrow0 + 2 * (P - R);
+        const bool rok = mrow >= 0 && mrow < ny;
+        *reinterpret_cast<uint2*>(mc + mw) = make_uint2(rok ? (va.x & ma0) : 0u, rok ? (va.y & ma1) : 0u);
+        *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) =
+            make_uint2(rok ? (vb.x & mb0) : 0u, rok ? (vb.y & mb1) : 0u);
+      }
       a1[fs] = b1[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
     }
   }
@@ -212,13 +220,23 @@ __device__ __forceinline__ void band2d_pair_tb2_body(const BandGrid& g, int w, u
 }
 
 template <int R, int OP, int ENG, bool ALIGNED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3 : 2))) void band2d_pair_tb2_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 && ALIGNED) ? 3 : 2))) void band2d_pair_tb2_kernel(
     BandGrid g) {
   constexpr int NP = R + 1;
   constexpr int UP = (NP >= 3) ? NP : 2 * NP;
   __shared__ uint32_t lds[(2 * UP + 4) * kPairRowDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
-  band2d_pair_tb2_body<R, OP, ENG, ALIGNED>(g, w, lds);
+  if constexpr (ENG == 1 && ALIGNED) {  // (a second body would spill the other variants)
+    // interior waves: columns [xp, xp + 256) and rows [y0 - 2R, y0 + hrows + 2R + 2) inside the grid
+    const int strip = w % g.nstrips, seg = w / g.nstrips;
+    const int xp = strip * kStripWPair2 - kPairWinLead;
+    const int y0 = seg * g.seg_h, hrows = min(g.seg_h, g.ny - y0);
+    if (xp >= 0 && xp + 256 <= g.nx && y0 - 2 * R >= 0 && y0 + hrows + 2 * R + 2 <= g.ny) {
+      band2d_pair_tb2_body<R, OP, ENG, ALIGNED, false>(g, w, lds);
+      return;
+    }
+  }
+  band2d_pair_tb2_body<R, OP, ENG, ALIGNED, true>(g, w, lds);
 }
 
 // ----------------------------------------------------------------------------- T fused steps
@@ -231,7 +249,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ENG == 1 ? 3
 // outside the grid and written to a two-slot LDS ring per level.  Each pass
 // computes 256 columns; values stay exact on a window that shrinks by r per
 // pass on either side, and the wave stores pair_tb_width(T, r) columns.
-template <int R, int OP, int ENG, bool ALIGNED, int T>
+// EDGE = false is the body of a wave whose every computed row and column lies
+// inside the grid, so its intermediate values need no zero-halo masking.
+template <int R, int OP, int ENG, bool ALIGNED, int T, bool EDGE>
 __device__ __forceinline__ void band2d_pair_tbt_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int NP = R + 1;
   constexpr int UP = (NP >= 3) ? NP : 2 * NP;
@@ -364,13 +384,20 @@ __device__ __forceinline__ void band2d_pair_tbt_body(const BandGrid& g, int w, u
       // grid, keep it for pass t + 1 at the next iteration
 #pragma unroll
       for (int t = 0; t + 1 < T; ++t) {
-        const int mrow = y0 - (T - 1 - t) * R + phi + 2 * (P - t * (R + 1) - R);
-        const bool rok = mrow >= 0 && mrow < ny;
+        // rows of the pair (the phi = 0 row is mrow0, wave-uniform)
+        const int mrow0 = y0 - (T - 1 - t) * R + 2 * (P - t * (R + 1) - R);
         const uint2 va = pack_out<OP>(acc_a[t][fs]), vb = pack_out<OP>(acc_b[t][fs]);
         uint32_t* mc = mid + (t * 2 + (P & 1)) * 2 * kPairRowDw;
-        *reinterpret_cast<uint2*>(mc + mw) = make_uint2(rok ? (va.x & ma0) : 0u, rok ? (va.y & ma1) : 0u);
-        *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) =
-            make_uint2(rok ? (vb.x & mb0) : 0u, rok ? (vb.y & mb1) : 0u);
+        if constexpr (!EDGE) {
+          // every row and column this wave computes lies inside the grid
+          *reinterpret_cast<uint2*>(mc + mw) = va;
+          *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) = vb;
+        } else {
+          const bool rok = (unsigned)(mrow0 + phi) < (unsigned)ny;
+          *reinterpret_cast<uint2*>(mc + mw) = make_uint2(rok ? (va.x & ma0) : 0u, rok ? (va.y & ma1) : 0u);
+          *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) =
+              make_uint2(rok ? (vb.x & mb0) : 0u, rok ? (vb.y & mb1) : 0u);
+        }
         acc_a[t][fs] = acc_b[t][fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
       }
     }
@@ -389,7 +416,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ba
   constexpr int UP = (NP >= 3) ? NP : 2 * NP;
   __shared__ uint32_t lds[(2 * UP + 4 * (T - 1)) * kPairRowDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
-  band2d_pair_tbt_body<R, OP, ENG, ALIGNED, T>(g, w, lds);
+  // interior waves (most of a large grid) skip the masking of intermediate values:
+  // columns [xp, xp + 256) and rows [y0 - T R, y0 + hrows + T R + 2) inside the grid
+  const int strip = w % g.nstrips, seg = w / g.nstrips;
+  const int xp = strip * pair_tb_width(T, R) - pair_tb_margin(T, R);
+  const int y0 = seg * g.seg_h, hrows = min(g.seg_h, g.ny - y0);
+  const bool interior = xp >= 0 && xp + 256 <= g.nx && y0 - T * R >= 0 && y0 + hrows + T * R + 2 <= g.ny;
+  (void)interior;
+  if constexpr (ENG == 1) {
+    if (interior) {
+      band2d_pair_tbt_body<R, OP, ENG, ALIGNED, T, false>(g, w, lds);
+      return;
+    }
+  }
+  // (the dense engine keeps one body: its second copy would spill)
+  band2d_pair_tbt_body<R, OP, ENG, ALIGNED, T, true>(g, w, lds);
 }
 
 namespace {
@@ -477,8 +518,9 @@ int occ_pair_tbt(int r, int operand, int engine) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
 #define SPIDER_OCC_PTT(RV, OPV, ENGV)                                                                    \
-  if (r == RV && operand == OPV && engine == ENGV)                                                       \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_pair_tbt_kernel<RV, OPV, ENGV, true, T>, 64, 0);
+  if constexpr (T == 3 || ENGV == 1)                                                                     \
+    if (r == RV && operand == OPV && engine == ENGV)                                                     \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band2d_pair_tbt_kernel<RV, OPV, ENGV, true, T>, 64, 0);
   SPIDER_OCC_PTT(1, 2, 1) SPIDER_OCC_PTT(2, 2, 1) SPIDER_OCC_PTT(3, 2, 1)
   SPIDER_OCC_PTT(1, 2, 2) SPIDER_OCC_PTT(2, 2, 2) SPIDER_OCC_PTT(3, 2, 2)
   SPIDER_OCC_PTT(1, 3, 1) SPIDER_OCC_PTT(2, 3, 1) SPIDER_OCC_PTT(3, 3, 1)
@@ -489,10 +531,12 @@ int occ_pair_tbt(int r, int operand, int engine) {
 }  // namespace
 
 hipError_t launch_band2d_pair_tbt(int r, int operand, int engine, int T, const BandGrid& g, hipStream_t s) {
+  // the dense engine fuses at most three steps (four spill its registers)
 #define SPIDER_PTT(OPV, ENGV)                                              \
   if (operand == OPV && engine == ENGV) {                                  \
     if (T == 3) return dispatch_pair_tbt_al<OPV, ENGV, 3>(r, g, s);        \
-    if (T == 4) return dispatch_pair_tbt_al<OPV, ENGV, 4>(r, g, s);        \
+    if constexpr (ENGV == 1)                                               \
+      if (T == 4) return dispatch_pair_tbt_al<OPV, ENGV, 4>(r, g, s);      \
   }
   SPIDER_PTT(2, 1) SPIDER_PTT(2, 2) SPIDER_PTT(3, 1) SPIDER_PTT(3, 2)
 #undef SPIDER_PTT
@@ -501,7 +545,7 @@ hipError_t launch_band2d_pair_tbt(int r, int operand, int engine, int T, const B
 
 int band2d_pair_tbt_blocks_per_cu(int r, int operand, int engine, int T) {
   if (T == 3) return occ_pair_tbt<3>(r, operand, engine);
-  if (T == 4) return occ_pair_tbt<4>(r, operand, engine);
+  if (T == 4 && engine == 1) return occ_pair_tbt<4>(r, operand, engine);
   return 0;
 }
 

@@ -281,7 +281,7 @@ __device__ __forceinline__ void band2d_pair_f32_body(const BandGrid& g, int w, u
 #undef SPIDER_PAIR_PASS
 
 template <int R, int OP, int ENG, bool ALIGNED, bool XLO, bool FUSED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 && !FUSED) ? 4 : (ENG == 1 ? 3 : 2))))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 && !FUSED) ? (ALIGNED ? 4 : 3) : 2)))
 void band2d_pair_f32_kernel(BandGrid g) {
   constexpr int PAIRSZ = 2 * (XLO ? 2 : 1) * kPairRowDw;
   __shared__ uint32_t lds[(FUSED ? 4 : 2) * PAIRSZ];

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
 // acc[m][b] holds output line (plane p - 2R + m, y = yb0 + b) while plane p is applied.
 
 template <typename T, int R, bool SKIPZ>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void direct3d_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && R >= 2) ? 1 : 2))) void direct3d_kernel(
     const T* __restrict__ in, T* __restrict__ out, int nz, int ny, int nx, const T* __restrict__ w, int seg_h,
     int nstrips, int nsegy) {
   using L = Line<T, R>;

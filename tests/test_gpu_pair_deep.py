@@ -161,3 +161,17 @@ def test_autotuned_depth(oracle_mod):
     # a second plan of the same shape reuses the cached choice
     again = sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True).info()
     assert (again["time_block"], again["tile_h2"]) == (info["time_block"], info["tile_h2"])
+
+
+@pytest.mark.parametrize("T", [3, 4])
+@pytest.mark.parametrize("tile", [16, 40])
+def test_interior_waves_integer_exact(oracle_mod, T, tile):
+    # waves whose rows and columns all lie inside the grid skip the zero-halo masking
+    # of intermediate values; a grid with many such waves must still match exactly
+    shape = (600, 1100)
+    for r in (1, 2, 3):
+        w = sparse_int_taps(r, 40 + r)
+        xd, x64 = to_dev(si.grid_integer(shape, -2, 2, 77 + r), "f16")
+        plan = sp.Plan(w, shape, carry="f16", band_height=8, time_block=T, tile_h=tile)
+        ref = oracle_mod.apply(w, x64, T)
+        assert np.array_equal(run(plan, xd, T), ref), r
