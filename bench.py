@@ -73,14 +73,15 @@ def timed_applies(torch, plan, xd, y, steps_per_pass, k, stream):
 
 
 def cone_samples(oracle, w, x64, steps, pts):
+    """The oracle at each sampled point, run on the point's dependency cone only."""
     r = (w.shape[0] - 1) // 2
-    ny, nx = x64.shape
     h = steps * r
     out = []
-    for (py, px) in pts:
-        y0, y1 = max(0, py - h), min(ny, py + h + 1)
-        x0, x1 = max(0, px - h), min(nx, px + h + 1)
-        out.append(oracle.apply(w, x64[y0:y1, x0:x1], steps)[py - y0, px - x0])
+    for p in pts:
+        lo = [max(0, c - h) for c in p]
+        hi = [min(n, c + h + 1) for n, c in zip(x64.shape, p)]
+        sub = x64[tuple(slice(a, b) for a, b in zip(lo, hi))]
+        out.append(oracle.apply(w, sub, steps)[tuple(c - a for c, a in zip(p, lo))])
     return np.array(out)
 
 
@@ -180,6 +181,38 @@ def batch3d(torch, sp, si, args):
     torch.cuda.synchronize()
     seq_ms = e0.elapsed_time(e1) / args.steps
     value = npts * args.steps / (total * 1e-3) / 1e9
+    # the plain fp32 GPU path (direct engine) on the same grids and steps
+    x32 = [x.to(torch.float32) for x in xs]
+    y32 = [torch.empty_like(x) for x in x32]
+    p32 = [sp.Plan(wl["coeffs"], wl["shape"], carry="f32") for wl in wls]
+    for p, x, y, st in zip(p32, x32, y32, steps):
+        p.apply(x, y, st)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for p, x, y, st in zip(p32, x32, y32, steps):
+        p.apply(x, y, st)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fp32_value = npts / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    errors = None
+    if not args.no_extras:
+        # the batched fp16 results against the fp64 oracle at sampled points (dependency cones)
+        import oracle
+        if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+            oracle.build()
+        rng = np.random.default_rng(0)
+        errors = {}
+        for wl, x, y, st in zip(wls, xs, ys, steps):
+            n = wl["shape"]
+            pts = [(0, 0, 0), tuple(v - 1 for v in n)] + [tuple(int(rng.integers(0, v)) for v in n) for _ in range(6)]
+            ref = cone_samples(oracle, wl["coeffs"], x.to(torch.float64).cpu().numpy(), st, pts)
+            got = y.to(torch.float64).cpu().numpy()
+            got = np.array([got[p] for p in pts])
+            d = got - ref
+            errors[wl["name"]] = {"rel_rms": float(np.sqrt((d * d).sum() / (ref * ref).sum())),
+                                  "rel_max": float(np.abs(d).max() / np.abs(ref).max()), "points": len(pts)}
+        ok = all(e["rel_rms"] <= TOL["f16"][0] and e["rel_max"] <= TOL["f16"][1] for e in errors.values())
+        errors["tol_rel_rms"], errors["tol_rel_max"], errors["pass"] = TOL["f16"][0], TOL["f16"][1], ok
     return {"metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": round(total / args.steps, 4), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
@@ -189,7 +222,10 @@ def batch3d(torch, sp, si, args):
                            "p99": round(float(np.percentile(per, 99)), 4)},
             "separate_plans": {"ms_per_step": round(seq_ms, 4),
                                "GStencil/s": round(npts / (seq_ms * 1e-3) / 1e9, 2),
-                               "tile_h": [p.info()["tile_h"] for p in solo]}}
+                               "tile_h": [p.info()["tile_h"] for p in solo]},
+            "plain_gpu_fp32": {"value": round(fp32_value, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
+                               "speedup_batched_lowp_over_fp32": round(value / fp32_value, 3)},
+            "error_vs_fp64_oracle": errors}
 
 
 def size_trend(torch, sp, si, args):
