@@ -164,12 +164,15 @@ spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int*
                                int* tile_h2, int* band_height);
 
 /*
- * Batched apply (one launch per time step over the tiles of every grid).
- * Runs grids of uneven size and stencil shape together: at time step s every
- * grid i with steps[i] > s advances by one step.  The plans must share the
- * carry dtype and use the sparse or dense engine; grids may be 2-D or 3-D.
- * Each grid's result equals spider_apply of a plan with time_block = 1 bit for
- * bit (and a fused plan's up to rounding, bit for bit where fusion is exact).
+ * Batched apply (launches over the tiles of every grid).
+ * Runs grids of uneven size and stencil shape together.  Launch k advances
+ * every grid that still has work: 2-D grids with paired-line bands by two fused
+ * time steps per launch (steps[i] / 2 launches, then one single step when
+ * steps[i] is odd), other grids by one step.  The plans must share the carry
+ * dtype and use the sparse or dense engine; grids may be 2-D or 3-D.
+ * Each grid's result equals spider_apply of a plan with time_block = 2 bit for
+ * bit (one step per launch where two cannot be fused; a plan fusing more steps
+ * agrees up to rounding).
  *   n       number of grids, 1..4096
  *   plans, ins, outs, steps: host arrays of n entries, as for spider_apply.
  * Errors: INVALID, UNSUPPORTED (mixed carries or direct-engine plans), HIP.

@@ -40,6 +40,8 @@ struct spider_plan_s {
   int tile_h2 = 0;                      // segment height of the fused kernel
   spider_impl::BandGrid grid_tb2{};     // fused kernel: 240-wide strips (two steps) or pair_tb_width
   spider_impl::BandGrid grid_batch{};   // one-step kernel inside batched launches (taller segments)
+  spider_impl::BandGrid grid_batch2{};  // two fused steps inside batched launches (paired bands)
+  bool batch_fuse = false;              // grid_batch2 is set: batches advance this grid two steps per launch
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
   std::mutex mu;

@@ -88,7 +88,8 @@ struct BatchArena {
   }
 };
 
-static int batch_kind(const spider_plan_s* p) {
+static int batch_kind(const spider_plan_s* p, bool fused) {
+  if (fused) return p->r == 1 ? kB2dPairTb2R1 : (p->r == 2 ? kB2dPairTb2R2 : kB2dPairTb2R3);
   if (p->ndim == 2 && p->band_h == 8) return p->r == 1 ? kB2dPairR1 : (p->r == 2 ? kB2dPairR2 : kB2dPairR3);
   if (p->ndim == 2) return p->r == 1 ? kB2dR1 : (p->r == 2 ? kB2dR2 : kB2dR3);
   // 3-D r = 1: star variant when every non-zero kernel row lies on the axes cross
@@ -177,7 +178,17 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     aligned = aligned && it.plan->nx % 8 == 0;
   }
   if (aligned) cls |= 4;  // aligned bodies only
-  // Per item: the first source, after the in == out copy when needed.
+  // Per item: its launches (grids with paired bands run steps / 2 launches of two
+  // fused steps, then a single step if steps is odd, as spider_apply with
+  // time_block 2 does), and the first source, after the in == out copy when needed.
+  std::vector<int> nl(n), nf(n);
+  int maxl = 0;
+  for (int i = 0; i < n; ++i) {
+    const BatchItem& it = items[i];
+    nf[i] = it.plan->batch_fuse ? it.steps / 2 : 0;
+    nl[i] = nf[i] + (it.steps - 2 * nf[i]);
+    maxl = std::max(maxl, nl[i]);
+  }
   std::vector<const void*> src(n);
   for (int i = 0; i < n; ++i) {
     const BatchItem& it = items[i];
@@ -188,7 +199,7 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
         hipError_t e = hipMemcpyAsync(it.out, it.in, bytes, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
       }
-    } else if (it.in == it.out && (it.steps - 1) % 2 == 0) {
+    } else if (it.in == it.out && (nl[i] - 1) % 2 == 0) {
       hipError_t e = hipMemcpyAsync(it.scratch, it.in, bytes, hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
       src[i] = it.scratch;
@@ -196,25 +207,25 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
   }
   if (maxsteps == 0) return SPIDER_OK;
   const int h3 = batch_height_3d(items);
-  // Descriptor layout per step: BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned.
-  std::vector<size_t> off(maxsteps + 1);
-  std::vector<int> m(maxsteps);
+  // Descriptor layout per launch: BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned.
+  std::vector<size_t> off(maxl + 1);
+  std::vector<int> m(maxl);
   size_t bytes = 0;
-  for (int st = 0; st < maxsteps; ++st) {
+  for (int st = 0; st < maxl; ++st) {
     int cnt = 0;
-    for (const auto& it : items) cnt += it.steps > st;
+    for (int i = 0; i < n; ++i) cnt += nl[i] > st;
     m[st] = cnt;
     off[st] = bytes;
     bytes += align_up(cnt * sizeof(BandGrid) + cnt * sizeof(int) + (cnt + 1) * sizeof(int), 256);
   }
-  off[maxsteps] = bytes;
+  off[maxl] = bytes;
 
   std::lock_guard<std::mutex> lk(A.mu);
   hipError_t e = A.reserve(bytes);
   if (e != hipSuccess) return hip_fail(e, "batch descriptor buffers");
   std::vector<const void*> cur = src;
-  std::vector<int> units(maxsteps, 0);
-  for (int st = 0; st < maxsteps; ++st) {
+  std::vector<int> units(maxl, 0);
+  for (int st = 0; st < maxl; ++st) {
     char* base = A.host + off[st];
     BandGrid* gd = reinterpret_cast<BandGrid*>(base);
     int* kinds = reinterpret_cast<int*>(base + m[st] * sizeof(BandGrid));
@@ -222,16 +233,17 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     int j = 0, acc = 0;
     for (int i = 0; i < n; ++i) {
       const BatchItem& it = items[i];
-      if (it.steps <= st) continue;
+      if (nl[i] <= st) continue;
       const int k = st + 1;
-      void* dst = ((it.steps - k) % 2 == 0) ? it.out : it.scratch;
-      BandGrid g = it.plan->grid_batch;
+      void* dst = ((nl[i] - k) % 2 == 0) ? it.out : it.scratch;
+      const bool fused = st < nf[i];
+      BandGrid g = fused ? it.plan->grid_batch2 : it.plan->grid_batch;
       if (it.plan->ndim == 3) set_height_3d(g, h3);
       g.in = cur[i];
       g.out = dst;
       cur[i] = dst;
       gd[j] = g;
-      kinds[j] = batch_kind(it.plan);
+      kinds[j] = batch_kind(it.plan, fused);
       begin[j] = acc;
       acc += g.nblocks;
       ++j;
@@ -241,7 +253,7 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
   }
   e = hipMemcpyAsync(A.dev, A.host, bytes, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-  for (int st = 0; st < maxsteps; ++st) {
+  for (int st = 0; st < maxl; ++st) {
     char* base = A.dev + off[st];
     const BandGrid* gd = reinterpret_cast<const BandGrid*>(base);
     const int* kinds = reinterpret_cast<const int*>(base + m[st] * sizeof(BandGrid));

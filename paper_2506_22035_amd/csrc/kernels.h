@@ -102,7 +102,8 @@ int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t 
 // Body selected per grid inside the batch kernel.
 enum BatchKind : int {
   kB2dR1 = 0, kB2dR2 = 1, kB2dR3 = 2, kB3dBox = 3, kB3dStar = 4,
-  kB2dPairR1 = 5, kB2dPairR2 = 6, kB2dPairR3 = 7  // paired-line bands (one step)
+  kB2dPairR1 = 5, kB2dPairR2 = 6, kB2dPairR3 = 7,      // paired-line bands (one step)
+  kB2dPairTb2R1 = 8, kB2dPairTb2R2 = 9, kB2dPairTb2R3 = 10  // paired-line bands, two fused steps
 };
 
 // One launch advancing every listed grid by one time step.

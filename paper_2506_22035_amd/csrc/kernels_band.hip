@@ -897,12 +897,13 @@ int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned) {
 // exactly begin[n] workgroups.  CLS selects the bodies compiled in: 1 = 2-D
 // kinds, 2 = 3-D kinds, 3 = all.
 template <int OP, int ENG, int CLS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 6 && ENG == 1) ? 3 : 2))) void band_batch_kernel(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(((CLS == 5 || CLS == 6) && ENG == 1) ? 3 : 2))) void band_batch_kernel(
     const BandGrid* __restrict__ grids, const int* __restrict__ kinds, const int* __restrict__ begin, int n) {
   // CLS bit 4: every grid's row length is a multiple of 8, so only the aligned
   // bodies are compiled in (the unaligned ones need more registers)
   constexpr bool k2d = (CLS & 1) != 0, k3d = (CLS & 2) != 0, al_only = (CLS & 4) != 0;
-  constexpr int kLds = (7 * kLdsRowDw + kLdsSpareDw) > (8 * kPairRowDw) ? (7 * kLdsRowDw + kLdsSpareDw) : (8 * kPairRowDw);
+  // the largest body: 16-point r = 3 (7 lines + spare) or two fused paired steps (12 lines)
+  constexpr int kLds = (7 * kLdsRowDw + kLdsSpareDw) > (12 * kPairRowDw) ? (7 * kLdsRowDw + kLdsSpareDw) : (12 * kPairRowDw);
   __shared__ uint32_t lds[kLds];
   const int total = begin[n];
   if ((int)blockIdx.x >= total) return;
@@ -931,6 +932,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((CLS == 6 &&
         break;
       case kB2dPairR3:
         if (al) band2d_pair_body<3, OP, ENG, true>(g, w, lds); else band2d_pair_body<3, OP, ENG, false>(g, w, lds);
+        break;
+      case kB2dPairTb2R1:
+        if (al) band2d_pair_tb2_body<1, OP, ENG, true, true>(g, w, lds);
+        else band2d_pair_tb2_body<1, OP, ENG, false, true>(g, w, lds);
+        break;
+      case kB2dPairTb2R2:
+        if (al) band2d_pair_tb2_body<2, OP, ENG, true, true>(g, w, lds);
+        else band2d_pair_tb2_body<2, OP, ENG, false, true>(g, w, lds);
+        break;
+      case kB2dPairTb2R3:
+        if (al) band2d_pair_tb2_body<3, OP, ENG, true, true>(g, w, lds);
+        else band2d_pair_tb2_body<3, OP, ENG, false, true>(g, w, lds);
         break;
       default:
         break;

@@ -34,191 +34,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ALIGNED ? 4 
 }
 
 // ----------------------------------------------------------------------------- two fused steps
-// Two time steps per launch on paired-line bands.  The first pass treats the
-// intermediate step's line pairs as its outputs, aligned so that they are
-// exactly the input pairs the second pass needs (rows y0 - r + 2m, m >= 0);
-// every finished intermediate pair is rounded to the carry type, zeroed outside
-// the grid, written to an LDS line pair in the staged-line layout and multiplied
-// again one input pair later (software-pipelined) into a second set of
-// accumulators.  The wave computes 256 columns per pass and stores the 240 in
-// [240 s, 240 s + 240): the intermediate values it lacks beyond its strip only
-// reach outputs it does not store.  For odd r the intermediate pairs start on
-// odd rows, unlike the one-step kernel's output pairs, so the fused result
-// agrees with two single steps to rounding, not bit for bit; it never depends
-// on the tiling.
-// EDGE = false: every row and column the wave computes lies inside the grid, so
-// the intermediate values need no zero-halo masking.
-template <int R, int OP, int ENG, bool ALIGNED, bool EDGE>
-__device__ __forceinline__ void band2d_pair_tb2_body(const BandGrid& g, int w, uint32_t* lds) {
-  constexpr int NP = R + 1;
-  constexpr int UP = (NP >= 3) ? NP : 2 * NP;
-  constexpr int NL = 2 * UP;
-  const int lane = threadIdx.x;
-  const int strip = w % g.nstrips, seg = w / g.nstrips;
-  const int xp = strip * kStripWPair2 - kPairWinLead;  // first column of both passes
-  const int y0 = seg * g.seg_h;
-  const int hrows = min(g.seg_h, g.ny - y0);
-  const int npin = (hrows + 1) / 2 + 2 * R + 1;       // input pairs streamed
-  const int nbody = (npin + UP - 1) / UP;
-  const int nx = g.nx, ny = g.ny;
-
-  u32x4 A[NP], D0[NP], D1[NP];
-  uint32_t I[(NP + 1) / 2];
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    if constexpr (ENG == 1) {
-      A[k] = reinterpret_cast<const u32x4*>(g.apack)[k * 64 + lane];
-      D0[k] = D1[k] = (u32x4){0, 0, 0, 0};
-    } else {
-      A[k] = (u32x4){0, 0, 0, 0};
-      D0[k] = reinterpret_cast<const u32x4*>(g.dpack)[(k * 64 + lane) * 2 + 0];
-      D1[k] = reinterpret_cast<const u32x4*>(g.dpack)[(k * 64 + lane) * 2 + 1];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < (NP + 1) / 2; ++k) I[k] = (ENG == 1) ? g.ipack[k * 64 + lane] : 0u;
-  __builtin_amdgcn_s_waitcnt(0);
-
-  int p1, p2;
-  pair_gather_offsets(lane, &p1, &p2);
-  const bool stager = lane < kPairChunks;
-  const uint32_t lvoff = stager ? (uint32_t)((xp - kPairWinLead + 8 * lane) * 2) : 0x7ffffff0u;
-  const int lw = 6 * lane;
-  // this lane's 4 values of either pass: columns xo + e (half a) and xo + 128 + e (half b)
-  // of line 2m + (lane >> 5) of the pair
-  const int xo = xp + 8 * (lane & 15) + 4 * ((lane >> 4) & 1);
-  const int phi = lane >> 5;
-  const int line_off = phi * nx;
-  const int x_lo = strip * kStripWPair2, x_hi = min(nx, x_lo + kStripWPair2);  // stored columns
-  uint32_t ova[4], ovb[4];
-  uint32_t ma0 = 0, ma1 = 0, mb0 = 0, mb1 = 0;  // 16-bit lanes of the intermediate values inside the grid
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int xa = xo + (ALIGNED ? 0 : e), xb = xa + 128;
-    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 2) : 0x7ffffff0u;
-    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 2) : 0x7ffffff0u;
-    const uint32_t half = (e & 1) ? 0xffff0000u : 0x0000ffffu;
-    const int ya = xo + e, yb = xo + 128 + e;
-    if (ya >= 0 && ya < nx) (e < 2 ? ma0 : ma1) |= half;
-    if (yb >= 0 && yb < nx) (e < 2 ? mb0 : mb1) |= half;
-  }
-  // intermediate LDS line pairs (two, alternating): this lane's 2 dwords of half a
-  // sit at data dword 4n + 2 + 2 (h & 1) of line phi; half b 96 dwords further
-  uint32_t* mid = lds + NL * kPairRowDw;
-  const int mw = 6 * (lane & 15) + (((lane >> 4) & 1) ? 6 : 2) + phi * kPairRowDw;
-  for (int i = lane; i < 4 * kPairRowDw; i += 64) mid[i] = 0u;
-
-  LineWalk lin(g.in, y0 - 2 * R, max(0, y0 - 2 * R), min(ny, y0 + hrows + 2 * R), nx * 2);
-  PairWalk pout(g.out, y0 - 2 * (2 * R + 1), y0, y0 + hrows, nx * 2);
-  u32x4 stg[NL];
-#pragma unroll
-  for (int l = 0; l < NL; ++l) stg[l] = load_chunk<ALIGNED>(lin.next(), lvoff);
-  f32x4 a1[NP], b1[NP], a2[NP], b2[NP];
-#pragma unroll
-  for (int s = 0; s < NP; ++s) a1[s] = b1[s] = a2[s] = b2[s] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  uint2 done_a[UP], done_b[UP];
-  // row of this lane's line in intermediate pair m: y0 - R + 2m + phi
-  const int mrow0 = y0 - R + phi;
-
-  for (int b = 0; b < nbody; ++b) {
-    wave_lds_sync();
-    if (stager) {
-#pragma unroll
-      for (int l = 0; l < NL; ++l) store_chunk_lds(lds, lw + l * kPairRowDw, stg[l]);
-    }
-    if (b > 0) {
-#pragma unroll
-      for (int q = 0; q < UP; ++q) {
-        const __amdgpu_buffer_rsrc_t rs = pout.next();
-        store_pair<ALIGNED>(rs, ova, done_a[q]);
-        store_pair<ALIGNED>(rs, ovb, done_b[q]);
-      }
-    }
-#pragma unroll
-    for (int l = 0; l < NL; ++l) stg[l] = load_chunk<ALIGNED>(lin.next(), lvoff);
-#pragma unroll
-    for (int q = 0; q < UP; ++q) {
-      const int P = b * UP + q;
-      wave_lds_sync();  // the intermediate pair written last iteration is visible
-      const uint32_t* l0 = lds + (2 * q) * kPairRowDw;
-      const uint32_t* l1 = l0 + kPairRowDw;
-      const uint32_t* m0 = mid + ((P + 1) & 1) * 2 * kPairRowDw;  // intermediate pair P - 1 - R
-      const uint32_t* m1 = m0 + kPairRowDw;
-      // first pass: input pair P -> intermediate pair P - k
-      {
-        const u32x4 x0 = pair_gather(l0, p1, p2), x1 = pair_gather(l1, p1, p2);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const int slot = ((q - k) % NP + NP) % NP;
-          if (k & 1)
-            a1[slot] = pair_mma<OP, ENG, 1>(a1[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-          else
-            a1[slot] = pair_mma<OP, ENG, 0>(a1[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-        }
-      }
-      {
-        const u32x4 x0 = pair_gather(l0 + kPairHalfDw, p1, p2), x1 = pair_gather(l1 + kPairHalfDw, p1, p2);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const int slot = ((q - k) % NP + NP) % NP;
-          if (k & 1)
-            b1[slot] = pair_mma<OP, ENG, 1>(b1[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-          else
-            b1[slot] = pair_mma<OP, ENG, 0>(b1[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-        }
-      }
-      // second pass: intermediate pair P - 1 - R -> output pair P - 1 - R - k, slot (q - k) mod NP
-      {
-        const u32x4 x0 = pair_gather(m0, p1, p2), x1 = pair_gather(m1, p1, p2);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const int slot = ((q - k) % NP + NP) % NP;
-          if (k & 1)
-            a2[slot] = pair_mma<OP, ENG, 1>(a2[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-          else
-            a2[slot] = pair_mma<OP, ENG, 0>(a2[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-        }
-      }
-      {
-        const u32x4 x0 = pair_gather(m0 + kPairHalfDw, p1, p2), x1 = pair_gather(m1 + kPairHalfDw, p1, p2);
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const int slot = ((q - k) % NP + NP) % NP;
-          if (k & 1)
-            b2[slot] = pair_mma<OP, ENG, 1>(b2[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-          else
-            b2[slot] = pair_mma<OP, ENG, 0>(b2[slot], A[k], D0[k], D1[k], I[k / 2], x0, x1);
-        }
-      }
-      const int fs = (q + 1) % NP;
-      // output pair P - 1 - 2R is complete
-      done_a[q] = pack_out<OP>(a2[fs]);
-      done_b[q] = pack_out<OP>(b2[fs]);
-      a2[fs] = b2[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      // intermediate pair P - R is complete: round, zero outside the grid, keep for the next iteration
-      const uint2 va = pack_out<OP>(a1[fs]), vb = pack_out<OP>(b1[fs]);
-      uint32_t* mc = mid + (P & 1) * 2 * kPairRowDw;
-      if constexpr (!EDGE) {
-        *reinterpret_cast<uint2*>(mc + mw) = va;
-        *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) = vb;
-      } else {
-        const int mrow = mrow0 + 2 * (P - R);
-        const bool rok = mrow >= 0 && mrow < ny;
-        *reinterpret_cast<uint2*>(mc + mw) = make_uint2(rok ? (va.x & ma0) : 0u, rok ? (va.y & ma1) : 0u);
-        *reinterpret_cast<uint2*>(mc + mw + kPairHalfDw) =
-            make_uint2(rok ? (vb.x & mb0) : 0u, rok ? (vb.y & mb1) : 0u);
-      }
-      a1[fs] = b1[fs] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < UP; ++q) {
-    const __amdgpu_buffer_rsrc_t rs = pout.next();
-    store_pair<ALIGNED>(rs, ova, done_a[q]);
-    store_pair<ALIGNED>(rs, ovb, done_b[q]);
-  }
-}
-
+// (the body, band2d_pair_tb2_body, is in band_pair.h: batched launches run it too)
 template <int R, int OP, int ENG, bool ALIGNED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 && ALIGNED) ? 3 : 2))) void band2d_pair_tb2_kernel(
     BandGrid g) {

@@ -191,6 +191,17 @@ void set_batch_geometry(spider_plan_s* p) {
     hb = std::min(p->ny, std::max(p->tile_h, 64));
     if (p->band_h == 8) hb += hb & 1;
     g.nsegs_y = (p->ny + hb - 1) / hb;
+    // paired bands with a 16-bit carry: batches run two fused steps per launch
+    p->batch_fuse = p->band_h == 8 && p->carry == p->operand && p->r <= 3 && !p->row_swap;
+    if (p->batch_fuse) {
+      BandGrid& g2 = p->grid_batch2;
+      g2 = p->grid_template;
+      g2.nstrips = (p->nx + kStripW2_host - 1) / kStripW2_host;
+      g2.seg_h = hb;
+      g2.nsegs_y = (p->ny + hb - 1) / hb;
+      g2.nsegs_z = 1;
+      g2.nblocks = g2.nstrips * g2.nsegs_y;
+    }
   } else {
     // the batched launch re-chooses one common 3-D height per batch
     hb = std::min(p->nz, 64);

@@ -125,12 +125,14 @@ def test_full_size_box2d49p_sampled(oracle_mod):
     assert rms <= TOL["f16"][0] and mx <= TOL["f16"][1]
 
 
-def test_batch_equals_unfused_apply():
-    # batched launches run one step each: equal to apply with time_block = 1, bit for bit
+def test_batch_equals_two_step_apply():
+    # batched launches run two fused steps, then one step for an odd count: equal to
+    # apply with time_block = 2, bit for bit (odd and even counts, in == out too)
     import torch
     rng = np.random.default_rng(17)
     plans, ins, outs, steps, alone = [], [], [], [], []
-    for r, shape, st in [(1, (130, 301), 5), (2, (77, 520), 4), (3, (203, 256), 6), (3, (9, 9), 3)]:
+    for r, shape, st in [(1, (130, 301), 5), (2, (77, 520), 4), (3, (203, 256), 6), (3, (9, 9), 3),
+                         (3, (600, 1040), 9), (1, (64, 700), 1)]:
         w = rng.uniform(0, 1, (2 * r + 1, 2 * r + 1))
         w /= w.sum()
         xd, _ = to_dev(rng.uniform(0, 1, shape), "f16")
@@ -138,10 +140,15 @@ def test_batch_equals_unfused_apply():
         ins.append(xd)
         outs.append(torch.empty_like(xd))
         steps.append(st)
-        alone.append(run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=1), xd, st))
+        alone.append(run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=2), xd, st))
     sp.apply_batch(plans, ins, outs, steps)
     for o, ref in zip(outs, alone):
         assert np.array_equal(from_dev(o), ref)
+    # in place (in == out), odd and even step counts
+    for p, x, st, ref in zip(plans, ins, steps, alone):
+        y = x.clone()
+        sp.apply_batch([p], [y], [y], [st])
+        assert np.array_equal(from_dev(y), ref)
 
 
 # ------------------------------------------------------------------ two fused steps per launch
