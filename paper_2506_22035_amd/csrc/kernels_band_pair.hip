@@ -191,6 +191,21 @@ __device__ __forceinline__ void band2d_pair_tbt_body(const BandGrid& g, int w, u
           }
         }
       }
+      // Schedule each group's gathers (4 LDS reads: two lines of one half) one group
+      // ahead of the previous group's matrix instructions, so the read latency
+      // overlaps matrix work instead of being waited for before every group.
+      // Measured: 1-3 % faster at T = 3; at T = 4 the register budget leaves no
+      // room for the extra operands and it was 1 % slower, so T = 4 keeps the
+      // compiler's own order.
+      if constexpr (T == 3) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+        for (int gi = 0; gi + 1 < 2 * T; ++gi) {
+          __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, NP, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, NP, 0);
+      }
       const int fs = (q + 1) % NP;
       // level-T pair P - (T - 1)(R + 1) - R is complete
       done_a[q] = pack_out<OP>(acc_a[T - 1][fs]);
