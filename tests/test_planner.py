@@ -8,6 +8,8 @@ the banded product (Sec. 3.1.1) and against the fp64 oracle.
 import ctypes
 import os
 import re
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -393,3 +395,19 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.spider_plan_destroy(None) == 0
     with pytest.raises(sp.SpiderError):
         sp.swap_columns(7, 1)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    # the product path has no fallback: with the library absent every call raises
+    code = (
+        "import numpy as np, paper_2506_22035_amd as sp\n"
+        "sp.LIB_PATH = %r\n"
+        "try:\n"
+        "    sp.Plan(np.ones((3, 3)) / 9, (64, 64))\n"
+        "except sp.SpiderError as e:\n"
+        "    print('raised', e)\n"
+        "else:\n"
+        "    print('no error')\n" % str(tmp_path / "libspider.so"))
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("raised") and "not built" in out.stdout, out.stdout
