@@ -74,9 +74,12 @@ typedef struct {
     int autotune;  /* 1 = when tile_h is 0, time candidate segment heights on the device at
                       plan time and keep the fastest (results cached per shape, radius,
                       engine and dtype for the life of the process); 0 = occupancy heuristic */
-    int time_block; /* time steps fused per launch: 0 = automatic (two for 2-D grids of
-                       radius <= 3 on the matrix engines with a 16-bit carry or with
-                       paired-line bands, else one),
+    int time_block; /* time steps fused per launch: 0 = automatic (paired-line bands with
+                       a 16-bit carry: four from 2^25 points, three from 2^23, else two;
+                       1-D lines with a 16-bit carry and radius <= 3: four from 2^22
+                       points, else two; other 2-D grids of radius <= 3 on the matrix
+                       engines with a 16-bit carry or with paired-line bands: two; else
+                       one; the dense engine fuses at most three),
                        1 = one step per launch, 2 = two where supported, 3 or 4 = that many
                        for paired-line bands with a 16-bit carry and for 1-D lines with
                        a 16-bit carry and radius <= 3 (else two where supported, else
@@ -116,8 +119,8 @@ spider_status spider_opts_default(spider_opts* o);
  * spider_plan: offline transformation (Sec. 3.1, done once per stencil; the paper
  * reports it as a small rule-based cost outside the timed loop, Sec. 4.2).
  *   coeffs  host fp64 array, (2r+1)^ndim, layout above; copied, not retained
- *   ndim    1, 2 or 3 (1-D lines run on the 16-point band engine, one step per launch,
- *           or on the direct engine)
+ *   ndim    1, 2 or 3 (1-D lines run on the 16-point band engine, one to four steps
+ *           per launch, or on the direct engine)
  *   shape   host array of ndim extents, each in [1, 2^31); a line (the last extent)
  *           may hold at most 2^30 - 1 bytes of state
  *   radius  1..7 (r = 7 is the largest radius the paper works through, Sec. 3.2)
@@ -155,7 +158,7 @@ spider_status spider_plan_destroy(spider_plan_t plan);
  *   (kernel rows on the matrix path; for paired-line bands the r + 1 instructions
  *   per input line pair), scratch_bytes (size of the grid-sized scratch buffer the
  *   plan allocates on first use), time_block (steps fused per launch), tile_h2
- *   (segment height of the two-step kernel, 0 if unused), band_height (output
+ *   (segment height of the fused kernel, 0 if time_block is 1), band_height (output
  *   points per band row: 16, or 8 for paired-line bands; 0 for the direct engine).
  *   Any output pointer may be NULL.
  */

@@ -373,7 +373,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     return fail(SPIDER_ERR_UNSUPPORTED, "band_height 8 (paired-line bands) needs a matrix engine, a 2-D grid and radius <= 3");
   if (o.row_swap != 0 && o.row_swap != 1) return fail(SPIDER_ERR_INVALID, "row_swap must be 0 or 1");
   if (o.row_swap == 1 && !(engine == SPIDER_ENGINE_SPARSE && low && ndim == 2 && o.band_height != 8 &&
-                           o.time_block != 2))
+                           o.time_block < 2))
     return fail(SPIDER_ERR_UNSUPPORTED,
                 "row_swap 1 (explicit) needs the sparse engine, a 16-bit carry, a 2-D grid, band height 16 and "
                 "one step per launch");

@@ -386,7 +386,7 @@ def test_invalid_arguments_rejected_without_gpu():
         o = opts(time_block=tb)
         assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
     # the explicit row swap: sparse engine, 16-bit carry, 2-D, band height 16, one step per launch
-    for kw in (dict(engine=2), dict(band_height=8), dict(time_block=2), dict(carry=1, engine=1, split=3)):
+    for kw in (dict(engine=2), dict(band_height=8), dict(time_block=2), dict(time_block=3), dict(time_block=4), dict(carry=1, engine=1, split=3)):
         o = opts(row_swap=1, **kw)
         assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2, kw
     o = opts(row_swap=1)
