@@ -57,6 +57,11 @@ __device__ __forceinline__ void band_gather_offsets(int lane, int* p1, int* p2) 
 // returns 0 for loads and drops stores outside [0, nx), which is exactly the
 // zero halo, with no per-lane branch.
 constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+// Byte offset of a lane that must not load or store: beyond the range of every
+// buffer resource built here (all cover less than 2^31 bytes: the planner caps a
+// line at 2^30 bytes and a resource spans at most two lines), with room for the
+// small per-element increments of unaligned accesses, which must not wrap it.
+constexpr uint32_t kOffNone = 0xffffff00u;
 
 // Sequential walk over consecutive lines of a grid (a stream of loads or of
 // stores).  next() returns the resource of the current line and advances one
@@ -102,7 +107,7 @@ __device__ __forceinline__ int staged_chunk(int lane) {
 // that is always out of range.  A negative x wraps to a huge unsigned offset,
 // which is out of range as well.
 __device__ __forceinline__ uint32_t chunk_voffset(int x0, int lane) {
-  return lane < kRowChunks ? (uint32_t)((x0 - 8 + 8 * lane) * 2) : 0x7ffffff0u;
+  return lane < kRowChunks ? (uint32_t)((x0 - 8 + 8 * lane) * 2) : kOffNone;
 }
 
 // Load this lane's chunk of a 16-bit line.

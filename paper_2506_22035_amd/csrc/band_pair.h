@@ -128,7 +128,7 @@ __device__ __forceinline__ void band2d_pair_body(const BandGrid& g, int w, uint3
   pair_gather_offsets(lane, &p1, &p2);
   // loads: lane c < 33 holds the 8 inputs at xs - 4 + 8c (half h's chunk n window = data dwords 64h + 4n ..+7)
   const bool stager = lane < kPairChunks;
-  const uint32_t lvoff = stager ? (uint32_t)((xs - kPairWinLead + 8 * lane) * 2) : 0x7ffffff0u;
+  const uint32_t lvoff = stager ? (uint32_t)((xs - kPairWinLead + 8 * lane) * 2) : kOffNone;
   const int lw = 6 * lane;
   // stores: lane (n, h) holds outputs x = xs + 128 half + 8n + 4 (h & 1) + e of line i + (h >> 1)
   const int xo = xs + 8 * (lane & 15) + 4 * ((lane >> 4) & 1);
@@ -137,8 +137,8 @@ __device__ __forceinline__ void band2d_pair_body(const BandGrid& g, int w, uint3
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int x = xo + (ALIGNED ? 0 : e);
-    ova[e] = (x >= 0 && x < nx) ? (uint32_t)((x + line_off) * 2) : 0x7ffffff0u;
-    ovb[e] = (x + 128 < nx) ? (uint32_t)((x + 128 + line_off) * 2) : 0x7ffffff0u;
+    ova[e] = (x >= 0 && x < nx) ? (uint32_t)((x + line_off) * 2) : kOffNone;
+    ovb[e] = (x + 128 < nx) ? (uint32_t)((x + 128 + line_off) * 2) : kOffNone;
   }
 
   LineWalk lin(g.in, y0 - R, max(0, y0 - R), min(ny, y0 + hrows + R), nx * 2);
@@ -259,7 +259,7 @@ __device__ __forceinline__ void band2d_pair_tb2_body(const BandGrid& g, int w, u
   int p1, p2;
   pair_gather_offsets(lane, &p1, &p2);
   const bool stager = lane < kPairChunks;
-  const uint32_t lvoff = stager ? (uint32_t)((xp - kPairWinLead + 8 * lane) * 2) : 0x7ffffff0u;
+  const uint32_t lvoff = stager ? (uint32_t)((xp - kPairWinLead + 8 * lane) * 2) : kOffNone;
   const int lw = 6 * lane;
   // this lane's 4 values of either pass: columns xo + e (half a) and xo + 128 + e (half b)
   // of line 2m + (lane >> 5) of the pair
@@ -272,8 +272,8 @@ __device__ __forceinline__ void band2d_pair_tb2_body(const BandGrid& g, int w, u
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int xa = xo + (ALIGNED ? 0 : e), xb = xa + 128;
-    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 2) : 0x7ffffff0u;
-    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 2) : 0x7ffffff0u;
+    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 2) : kOffNone;
+    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 2) : kOffNone;
     const uint32_t half = (e & 1) ? 0xffff0000u : 0x0000ffffu;
     const int ya = xo + e, yb = xo + 128 + e;
     if (ya >= 0 && ya < nx) (e < 2 ? ma0 : ma1) |= half;

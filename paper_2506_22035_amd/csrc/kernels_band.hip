@@ -221,7 +221,7 @@ __device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* 
   const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
   auto load_blk = [&](int j) {  // block b0 + j, zero beyond the segment
     const int x = 256 * (b0 + j) + lx;
-    const uint32_t off = (j < nb && lane < kRowChunks) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    const uint32_t off = (j < nb && lane < kRowChunks) ? (uint32_t)(x * 2) : kOffNone;
     return load_chunk<ALIGNED>(rin, off);
   };
   u32x4 stg[U];
@@ -240,7 +240,7 @@ __device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* 
       for (int q = 0; q < U; ++q) {
         const int j = jb - U + q;
         const int x = 256 * (b0 + j) + ox;
-        const uint32_t off = (j < nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+        const uint32_t off = (j < nb && x >= 0) ? (uint32_t)(x * 2) : kOffNone;
         store_packed<ALIGNED>(rout, off, done[q]);
       }
     }
@@ -259,7 +259,7 @@ __device__ __forceinline__ void band1d_body(const BandGrid& g, int w, uint32_t* 
   for (int q = 0; q < U; ++q) {
     const int j = nbody * U - U + q;
     const int x = 256 * (b0 + j) + ox;
-    const uint32_t off = (j < nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    const uint32_t off = (j < nb && x >= 0) ? (uint32_t)(x * 2) : kOffNone;
     store_packed<ALIGNED>(rout, off, done[q]);
   }
 }
@@ -344,7 +344,7 @@ __device__ __forceinline__ void band1d_tbt_body(const BandGrid& g, int w, uint32
 
   auto load_blk = [&](int it) {  // input block s0 + it, zero where level 1 does not need it
     const int x = 256 * (s0 + it) + lx;
-    const uint32_t off = (it < nin && lane < kRowChunks) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    const uint32_t off = (it < nin && lane < kRowChunks) ? (uint32_t)(x * 2) : kOffNone;
     return load_chunk<ALIGNED>(rin, off);
   };
   u32x4 stg[U];
@@ -363,7 +363,7 @@ __device__ __forceinline__ void band1d_tbt_body(const BandGrid& g, int w, uint32
       for (int q = 0; q < U; ++q) {
         const int k = s0 + (jb - U + q) - 2 * (T - 1);  // output block of that iteration
         const int x = 256 * k + ox;
-        const uint32_t off = (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+        const uint32_t off = (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 2) : kOffNone;
         store_packed<ALIGNED>(rout, off, done[q]);
       }
     }
@@ -409,7 +409,7 @@ __device__ __forceinline__ void band1d_tbt_body(const BandGrid& g, int w, uint32
   for (int q = 0; q < U; ++q) {
     const int k = s0 + (nbody * U - U + q) - 2 * (T - 1);
     const int x = 256 * k + ox;
-    const uint32_t off = (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 2) : 0x7ffffff0u;
+    const uint32_t off = (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 2) : kOffNone;
     store_packed<ALIGNED>(rout, off, done[q]);
   }
 }
@@ -500,7 +500,7 @@ __device__ __forceinline__ void band2d_tb2_body(const BandGrid& g, int w, uint32
   band_gather_offsets(lane, &p1, &p2);
   const uint32_t lvoff = chunk_voffset(x0 - 8, lane);       // staged line covers [x0 - 16, x0 + 256)
   const int xl = x0 - 8 + 16 * (lane & 15) + 4 * (lane >> 4);  // this lane's 4 outputs of either pass
-  const uint32_t ovoff = (xl >= x0 && xl < x0 + kStripW2) ? (uint32_t)(xl * 2) : 0x7ffffff0u;
+  const uint32_t ovoff = (xl >= x0 && xl < x0 + kStripW2) ? (uint32_t)(xl * 2) : kOffNone;
   // 16-bit lanes of the packed intermediate values that lie inside the grid (zero halo)
   const uint32_t xm0 = (xl >= 0 && xl < nx ? 0x0000ffffu : 0u) | (xl + 1 >= 0 && xl + 1 < nx ? 0xffff0000u : 0u);
   const uint32_t xm1 = (xl + 2 >= 0 && xl + 2 < nx ? 0x0000ffffu : 0u) | (xl + 3 >= 0 && xl + 3 < nx ? 0xffff0000u : 0u);

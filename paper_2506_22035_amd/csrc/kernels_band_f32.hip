@@ -116,7 +116,7 @@ __device__ __forceinline__ void band2d_f32_body(const BandGrid& g, int w, uint32
   band_gather_offsets(lane, &p1, &p2);
   // byte offsets of this lane's loads within a line; negative x wraps out of range
   const uint32_t mvoff = (uint32_t)((x0 - 8 + 4 * lane) * 4);
-  const uint32_t tvoff = lane < 16 ? (uint32_t)((x0 + 248 + lane) * 4) : 0x7ffffff0u;
+  const uint32_t tvoff = lane < 16 ? (uint32_t)((x0 + 248 + lane) * 4) : kOffNone;
   const uint32_t ovoff = (uint32_t)((x0 + 16 * (lane & 15) + 4 * (lane >> 4)) * 4);
   // LDS: U input lines x NL 16-bit lines of kLdsRowDw dwords, then a spare area
   const int spare_tw = (U * NL * kLdsRowDw) * 4;

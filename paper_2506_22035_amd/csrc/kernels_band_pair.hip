@@ -103,7 +103,7 @@ __device__ __forceinline__ void band2d_pair_tbt_body(const BandGrid& g, int w, u
   int p1, p2;
   pair_gather_offsets(lane, &p1, &p2);
   const bool stager = lane < kPairChunks;
-  const uint32_t lvoff = stager ? (uint32_t)((xp - kPairWinLead + 8 * lane) * 2) : 0x7ffffff0u;
+  const uint32_t lvoff = stager ? (uint32_t)((xp - kPairWinLead + 8 * lane) * 2) : kOffNone;
   const int lw = 6 * lane;
   // this lane's 4 values of every pass: columns xo + e (half a) and xo + 128 + e (half b)
   // of line 2m + (lane >> 5) of the pair
@@ -116,8 +116,8 @@ __device__ __forceinline__ void band2d_pair_tbt_body(const BandGrid& g, int w, u
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int xa = xo + (ALIGNED ? 0 : e), xb = xa + 128;
-    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 2) : 0x7ffffff0u;
-    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 2) : 0x7ffffff0u;
+    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 2) : kOffNone;
+    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 2) : kOffNone;
     const uint32_t half = (e & 1) ? 0xffff0000u : 0x0000ffffu;
     const int ya = xo + e, yb = xo + 128 + e;
     if (ya >= 0 && ya < nx) (e < 2 ? ma0 : ma1) |= half;

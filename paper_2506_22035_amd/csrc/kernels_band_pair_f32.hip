@@ -145,7 +145,7 @@ __device__ __forceinline__ void band2d_pair_f32_body(const BandGrid& g, int w, u
   pair_gather_offsets(lane, &p1, &p2);
   // loads (byte offsets in an fp32 line): 4 values at xp - 4 + 4 lane, lanes < 8 one more at xp + 252 + lane
   const uint32_t mvoff = (uint32_t)((xp - kPairWinLead + 4 * lane) * 4);
-  const uint32_t tvoff = lane < 8 ? (uint32_t)((xp + 252 + lane) * 4) : 0x7ffffff0u;
+  const uint32_t tvoff = lane < 8 ? (uint32_t)((xp + 252 + lane) * 4) : kOffNone;
   const int mw = 6 * (lane >> 1) + 2 * (lane & 1);           // data dwords 2 lane, 2 lane + 1
   const int tw = (6 * 32 + (lane >> 1)) * 4 + 2 * (lane & 1);  // data half 256 + lane (lane < 8)
   // stores: lane (n, h) holds x = xp + 128 half + 8n + 4 (h & 1) + e of line 2m + (lane >> 5)
@@ -159,8 +159,8 @@ __device__ __forceinline__ void band2d_pair_f32_body(const BandGrid& g, int w, u
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int xa = xo + (ALIGNED ? 0 : e), xb = xa + 128;
-    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 4) : 0x7ffffff0u;
-    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 4) : 0x7ffffff0u;
+    ova[e] = (xa >= x_lo && xa < x_hi) ? (uint32_t)((xa + line_off) * 4) : kOffNone;
+    ovb[e] = (xb >= x_lo && xb < x_hi) ? (uint32_t)((xb + line_off) * 4) : kOffNone;
     ma[e] = (xo + e >= 0 && xo + e < nx) ? 0xffffffffu : 0u;
     mb[e] = (xo + 128 + e < nx) ? 0xffffffffu : 0u;
   }

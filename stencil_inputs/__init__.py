@@ -125,6 +125,13 @@ def grid_integer(shape, lo, hi, seed, dtype=np.float32):
     return rng.integers(lo, hi + 1, shape).astype(dtype)
 
 
+def grid_integer_int8(shape, lo, hi, seed):
+    """Integer grid values drawn uniformly from [lo, hi] (-128 <= lo <= hi <= 127),
+    drawn directly as int8 so grids of 2^31 points stay at one byte per point."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(lo, hi + 1, shape, dtype=np.int8)
+
+
 def grid_sinusoids(shape, seed, dtype=np.float32, nwaves=8, noise=0.01):
     """Smooth 2-D field: mean of `nwaves` random plane sinusoids plus uniform noise.
 
