@@ -134,3 +134,52 @@ def test_tall_narrow_grids(oracle_mod, nx):
     check(oracle_mod, int_taps(2, 3, 9), shape, "f16",
           [dict(band_height=8, time_block=1), dict(band_height=8, time_block=4),
            dict(band_height=16, time_block=1), dict(band_height=16, time_block=2)], 17)
+
+
+def test_longest_lines_direct_engine(oracle_mod):
+    # fp32 1-D: 2^28 - 1 points (2^30 - 4 bytes); fp64 2-D: lines of 2^27 - 1 points
+    print("1-D fp32 direct", flush=True)
+    check(oracle_mod, int_taps(1, 3, 21), ((1 << 28) - 1,), "f32", [dict(engine="direct")], 31)
+    import torch
+    shape = (2, (1 << 27) - 1)
+    print("2-D fp64 direct", shape, flush=True)
+    w = int_taps(2, 2, 22)
+    x8 = si.grid_integer_int8(shape, -2, 2, 32)
+    x = torch.from_numpy(x8).to("cuda:0").to(torch.float64)
+    y = torch.empty_like(x)
+    plan = sp.Plan(w, shape, carry="f64")
+    plan.apply(x, y, STEPS)
+    torch.cuda.synchronize()
+    plan.close()
+    pts = sample_points(shape, 32)
+    assert np.array_equal(np.array([float(y[p]) for p in pts]), cone_values(oracle_mod, w, x8, STEPS, pts))
+
+
+def test_longest_line_3d(oracle_mod):
+    shape = (3, 2, (1 << 29) - 1)
+    print("3-D", shape, flush=True)
+    check(oracle_mod, int_taps(3, 1, 23), shape, "f16", [dict(time_block=1)], 33)
+
+
+def test_batch_at_the_limits():
+    # a batched launch over the longest paired-band line, the longest 16-point line
+    # and a 3-D grid: each equals its own apply with time_block = 2
+    import torch
+    cases = [((5, (1 << 28) - 1), int_taps(2, 3, 41), dict(band_height=8)),
+             ((3, (1 << 29) - 1), int_taps(2, 2, 42), dict(band_height=16)),
+             ((40, 64, 1000), int_taps(3, 1, 43), dict())]
+    plans, xs, ys, refs = [], [], [], []
+    for i, (shape, w, kw) in enumerate(cases):
+        print("batch grid", shape, flush=True)
+        x = torch.from_numpy(si.grid_integer_int8(shape, -2, 2, 50 + i)).to("cuda:0").to(torch.float16)
+        p = sp.Plan(w, shape, carry="f16", **kw)
+        r = torch.empty_like(x)
+        sp.Plan(w, shape, carry="f16", time_block=2, **kw).apply(x, r, STEPS)
+        plans.append(p)
+        xs.append(x)
+        ys.append(torch.empty_like(x))
+        refs.append(r)
+    sp.apply_batch(plans, xs, ys, [STEPS] * len(cases))
+    torch.cuda.synchronize()
+    for y, r, (shape, _, _) in zip(ys, refs, cases):
+        assert torch.equal(y, r), shape
