@@ -131,7 +131,8 @@ spider_status spider_opts_default(spider_opts* o);
  * to 2:4 values + 2-bit indices and packs them in the gfx950 lane order and uploads
  * them to the current HIP device.  A grid-sized scratch buffer is allocated on the
  * first spider_apply / spider_apply_batch (or at plan time when autotuning).
- * Errors: INVALID (arguments), UNSUPPORTED (e.g. a matrix engine with an fp64 carry,
+ * Errors: INVALID (arguments; on the matrix engines also a coefficient whose 16-bit
+ * rounding overflows, |w| > 65504 for fp16), UNSUPPORTED (e.g. a matrix engine with an fp64 carry,
  * or with an fp32 carry on a 3-D grid), OOM, HIP.  The plan is immutable after
  * creation and owns its device memory.
  */

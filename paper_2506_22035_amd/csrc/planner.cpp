@@ -156,6 +156,10 @@ bool pack_row(const double* row, int r, int operand, int split, PackedRow* out, 
   uint16_t hib[15], lob[15];
   for (int t = 0; t < kw; ++t) {
     hi[t] = operand == 2 ? round_f16(row[t], &hib[t]) : round_bf16(row[t], &hib[t]);
+    if (!std::isfinite(hi[t])) {
+      if (err) *err = "a coefficient lies beyond the range of the 16-bit operand type";
+      return false;
+    }
     const double rest = row[t] - hi[t];  // exact in fp64
     if (split == 2) {
       lo[t] = operand == 2 ? round_f16(rest, &lob[t]) : round_bf16(rest, &lob[t]);
@@ -252,6 +256,10 @@ bool pack_pair(const double* w, int r, int operand, int split, int k, PackedRow*
   uint16_t hib[49], lob[49];
   for (int t = 0; t < kw * kw; ++t) {
     hi[t] = operand == 2 ? round_f16(w[t], &hib[t]) : round_bf16(w[t], &hib[t]);
+    if (!std::isfinite(hi[t])) {
+      if (err) *err = "a coefficient lies beyond the range of the 16-bit operand type";
+      return false;
+    }
     if (split == 2) {
       const double rest = w[t] - hi[t];
       lo[t] = operand == 2 ? round_f16(rest, &lob[t]) : round_bf16(rest, &lob[t]);

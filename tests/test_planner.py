@@ -411,3 +411,15 @@ def test_binding_fails_loudly_without_library(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.startswith("raised") and "not built" in out.stdout, out.stdout
+
+
+def test_coefficient_beyond_operand_range_rejected():
+    # fp16 operands hold |w| <= 65504; bf16 reaches ~3.4e38
+    for v in (7e4, -1e6):
+        row = np.array([0.25, v, 0.25])
+        with pytest.raises(sp.SpiderError):
+            sp.pack_row(row, 1, "f16", 2)
+        with pytest.raises(sp.SpiderError):
+            sp.pack_pair(np.full((3, 3), v), 1, 0, "f16", 2)
+        sp.pack_row(row, 1, "bf16", 2)
+    sp.pack_row(np.array([0.25, 65504.0, 0.25]), 1, "f16", 2)
