@@ -146,6 +146,11 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
  *   steps    >= 0
  * The plan's scratch buffer holds intermediate steps, so two applies of one plan
  * must not overlap in time (use one plan per concurrent stream).
+ * With use_graph, a loop of at most 512 launches is captured once per (in, out,
+ * steps) as one graph and replayed; a longer loop replays one cached graph per
+ * 256-launch body (so graphs stay bounded in size) and launches the remainder
+ * directly.  The caches hold at most 64 and 16 graphs per plan; evicting one
+ * waits for the device first.
  * Errors: INVALID (null plan/pointer, steps < 0), HIP (launch failure).
  */
 spider_status spider_apply(spider_plan_t plan, const void* in, void* out, int steps, void* stream);

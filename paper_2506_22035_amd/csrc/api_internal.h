@@ -44,6 +44,9 @@ struct spider_plan_s {
   bool batch_fuse = false;              // grid_batch2 is set: batches advance this grid two steps per launch
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
+  // long time loops: one graph of kGraphBody launches of one kind (fused or single)
+  // between two buffers, replayed; keyed by (fused, first source, first destination)
+  std::map<std::tuple<bool, const void*, const void*>, hipGraphExec_t> body_graphs;
   std::mutex mu;
 };
 
@@ -63,6 +66,10 @@ void set_tile2(spider_plan_s* p, int h);
 // Geometry of the plan's work units inside batched launches (from its current tile height).
 void set_batch_geometry(spider_plan_s* p);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
+// Launches per replayed graph body of a long time loop (even); loops of more than
+// twice as many launches replay bodies instead of capturing the whole loop.
+constexpr int kGraphBody = 256;
+spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, int fused, int total, hipStream_t s);
 // Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).
 spider_status autotune_tile(spider_plan_s* p);
 }  // namespace spider_impl

@@ -271,34 +271,125 @@ void set_time_block(spider_plan_s* p, int T, int tile_h) {
 // b_1 .. b_L (L launches) with b_L = out, alternating between out and the plan's
 // scratch so that the last launch lands in out and `in` is never written (unless
 // in == out).
-spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s) {
-  const size_t bytes = p->grid_bytes;
-  if (steps == 0) {
-    if (in != out) {
-      hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    }
-    return SPIDER_OK;
-  }
+// The launches of a time loop of `steps` steps: `fused` of time_block steps, then
+// single steps; `total` in all.
+static void loop_launches(const spider_plan_s* p, int steps, int* fused, int* total) {
   const int tb = p->time_block;
-  const int pairs = tb >= 2 ? steps / tb : 0;  // fused launches of tb steps, then single steps
-  const int launches = pairs + (steps - tb * pairs);
-  const void* src = in;
-  // b_k = out if (L - k) is even, else scratch.  With in == out and b_1 == out
-  // (L odd), launch 1 would read and write one buffer: copy in to scratch first.
-  if (in == out && (launches - 1) % 2 == 0) {
-    hipError_t e = hipMemcpyAsync(p->d_scratch, in, bytes, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    src = p->d_scratch;
-  }
-  for (int k = 1; k <= launches; ++k) {
-    void* dst = ((launches - k) % 2 == 0) ? out : p->d_scratch;
+  *fused = tb >= 2 ? steps / tb : 0;
+  *total = *fused + (steps - tb * *fused);
+}
+
+// Launches k in [k0, k1] of a loop of `total` launches (`fused` of them fused),
+// reading `src` first.  Buffers b_k = out if (total - k) is even, else scratch.
+static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* out, int k0, int k1, int fused,
+                                      int total, hipStream_t s) {
+  for (int k = k0; k <= k1; ++k) {
+    void* dst = ((total - k) % 2 == 0) ? out : p->d_scratch;
     if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: launch %d reads and writes one buffer", k);
-    spider_status st = (k <= pairs) ? launch_step2(p, src, dst, s) : launch_step(p, src, dst, s);
+    spider_status st = (k <= fused) ? launch_step2(p, src, dst, s) : launch_step(p, src, dst, s);
     if (st != SPIDER_OK) return st;
     src = dst;
   }
   return SPIDER_OK;
+}
+
+// The buffer launch 1 reads: `in`, or the scratch copy of it when in == out and
+// launch 1 would write out (copied here).
+static spider_status first_source(spider_plan_s* p, const void* in, void* out, int total, hipStream_t s,
+                                  const void** src) {
+  *src = in;
+  if (in == out && (total - 1) % 2 == 0) {
+    hipError_t e = hipMemcpyAsync(p->d_scratch, in, p->grid_bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    *src = p->d_scratch;
+  }
+  return SPIDER_OK;
+}
+
+spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s) {
+  if (steps == 0) {
+    if (in != out) {
+      hipError_t e = hipMemcpyAsync(out, in, p->grid_bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return SPIDER_OK;
+  }
+  int fused, total;
+  loop_launches(p, steps, &fused, &total);
+  const void* src;
+  spider_status st = first_source(p, in, out, total, s, &src);
+  if (st != SPIDER_OK) return st;
+  return enqueue_launches(p, src, out, 1, total, fused, total, s);
+}
+
+// Capture the launches enqueued by `body` on the plan's capture stream as one
+// executable graph.
+template <class F>
+static spider_status capture(spider_plan_s* p, F body, hipGraphExec_t* exec) {
+  if (!p->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  }
+  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+  spider_status st = body(p->cap_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &graph);
+  if (st != SPIDER_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return SPIDER_OK;
+}
+
+// A time loop of more than 2 kGraphBody launches: launch 1 directly, then every
+// whole body of kGraphBody launches of one kind (fused, then single) as a replay
+// of one cached graph, the rest directly.  kGraphBody is even, so a body leaves
+// its result in the buffer it started from and one graph serves every body
+// between the same two buffers.
+spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, int fused, int total, hipStream_t s) {
+  static_assert(kGraphBody % 2 == 0, "a body must return to its first source");
+  const void* src;
+  spider_status st = first_source(p, in, out, total, s, &src);
+  if (st == SPIDER_OK) st = enqueue_launches(p, src, out, 1, 1, fused, total, s);
+  int k = 2;
+  while (st == SPIDER_OK && k <= total) {
+    const bool kind = k <= fused;
+    const int run_end = kind ? fused : total;  // last launch of this kind
+    while (st == SPIDER_OK && run_end - k + 1 >= kGraphBody) {
+      const void* from = ((total - (k - 1)) % 2 == 0) ? out : p->d_scratch;
+      void* to = ((total - k) % 2 == 0) ? out : p->d_scratch;
+      auto key = std::make_tuple(kind, from, (const void*)to);
+      auto it = p->body_graphs.find(key);
+      if (it == p->body_graphs.end()) {
+        hipGraphExec_t exec = nullptr;
+        // launches k .. k + kGraphBody - 1 of this loop: the same for every body
+        st = capture(p, [&](hipStream_t cs) {
+          return enqueue_launches(p, from, out, k, k + kGraphBody - 1, fused, total, cs);
+        }, &exec);
+        if (st != SPIDER_OK) return st;
+        if (p->body_graphs.size() >= 16) {  // bound the cache (rare: waits for queued work first)
+          hipDeviceSynchronize();
+          hipGraphExecDestroy(p->body_graphs.begin()->second);
+          p->body_graphs.erase(p->body_graphs.begin());
+        }
+        it = p->body_graphs.emplace(key, exec).first;
+      }
+      hipError_t e = hipGraphLaunch(it->second, s);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      k += kGraphBody;
+    }
+    if (st == SPIDER_OK && k <= run_end) {
+      const void* from = ((total - (k - 1)) % 2 == 0) ? out : p->d_scratch;
+      st = enqueue_launches(p, from, out, k, run_end, fused, total, s);
+      k = run_end + 1;
+    }
+  }
+  return st;
 }
 
 }  // namespace spider_impl
@@ -537,29 +628,18 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
     if (st != SPIDER_OK) return st;
   }
   if (!p->use_graph || steps < 2) return enqueue_steps(p, in, out, steps, s);
+  int fused, total;
+  loop_launches(p, steps, &fused, &total);
+  if (total > 2 * kGraphBody) return enqueue_long(p, in, out, fused, total, s);
   // Replay a graph of the whole time loop, captured once per (in, out, steps).
   auto key = std::make_tuple(in, (const void*)out, steps);
   auto it = p->graphs.find(key);
   if (it == p->graphs.end()) {
-    if (!p->cap_stream) {
-      hipError_t e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-    }
-    hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    spider_status st = enqueue_steps(p, in, out, steps, p->cap_stream);
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(p->cap_stream, &graph);
-    if (st != SPIDER_OK) {
-      if (graph) hipGraphDestroy(graph);
-      return st;
-    }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    if (p->graphs.size() >= 64) {  // bound the cache
+    spider_status st = capture(p, [&](hipStream_t cs) { return enqueue_steps(p, in, out, steps, cs); }, &exec);
+    if (st != SPIDER_OK) return st;
+    if (p->graphs.size() >= 64) {  // bound the cache (rare: waits for queued work first)
+      hipDeviceSynchronize();
       hipGraphExecDestroy(p->graphs.begin()->second);
       p->graphs.erase(p->graphs.begin());
     }
@@ -573,6 +653,7 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
 spider_status spider_plan_destroy(spider_plan_t p) {
   if (!p) return SPIDER_OK;
   for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : p->body_graphs) hipGraphExecDestroy(kv.second);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
   if (p->d_apack) hipFree(p->d_apack);
   if (p->d_ipack) hipFree(p->d_ipack);

@@ -155,6 +155,33 @@ def test_graph_replay_equals_eager_and_is_deterministic():
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("T", [1, 2, 4])
+def test_long_loops_replay_bodies(oracle_mod, T):
+    # loops of more than 512 launches replay one graph per 256-launch body: they must
+    # equal launches without graphs, also in place and with a remainder of each kind
+    import torch
+    rng = np.random.default_rng(7)
+    w = rng.uniform(0, 1, (5, 5))
+    w /= w.sum()
+    shape = (70, 300)
+    xd, x64 = to_dev(rng.uniform(0, 1, shape), "f16")
+    for steps in (513 * T + (T - 1), 1100 * T + 1):
+        plan_g = sp.Plan(w, shape, carry="f16", band_height=8, time_block=T)
+        plan_e = sp.Plan(w, shape, carry="f16", band_height=8, time_block=T, use_graph=False)
+        assert plan_g.info()["time_block"] == T
+        ref = run(plan_e, xd, steps)
+        for _ in range(2):   # the second call replays cached bodies
+            assert np.array_equal(run(plan_g, xd, steps), ref), steps
+        y = xd.clone()
+        plan_g.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), ref), steps
+    # 600 steps stay close to the oracle (a per-step fp16 rounding emulated on the
+    # host errs by 2.6e-4 / 6.2e-4 here; the bound leaves 10x or more)
+    got = run(plan_g, xd, 600)
+    rms, mx = rel_errors(got, oracle_mod.apply(w, x64, 600))
+    assert rms <= 5e-3 and mx <= 1e-2, (rms, mx)
+
+
 def test_tile_heights_agree():
     import torch
     wl = si.workload("star2d13p_8192", small=True)
