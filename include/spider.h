@@ -151,7 +151,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
  * 256-launch body (so graphs stay bounded in size) and launches the remainder
  * directly.  The caches hold at most 64 and 16 graphs per plan; evicting one
  * waits for the device first.
- * Errors: INVALID (null plan/pointer, steps < 0), HIP (launch failure).
+ * Errors: INVALID (null plan/pointer, steps < 0, or a device other than the one
+ * current at spider_plan is current), HIP (launch failure).
  */
 spider_status spider_apply(spider_plan_t plan, const void* in, void* out, int steps, void* stream);
 
@@ -184,7 +185,8 @@ spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int*
  * agrees up to rounding).
  *   n       number of grids, 1..4096
  *   plans, ins, outs, steps: host arrays of n entries, as for spider_apply.
- * Errors: INVALID, UNSUPPORTED (mixed carries or direct-engine plans), HIP.
+ * Errors: INVALID (also: a plan of another device than the current one),
+ * UNSUPPORTED (mixed carries or direct-engine plans), HIP.
  */
 spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* const* ins,
                                  void* const* outs, const int* steps, void* stream);
@@ -206,7 +208,8 @@ spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int m
  * spider_submit: enqueue out = S^steps(in) for `plan`.  `in` and `out` are
  * device buffers owned by the caller that must stay valid until the ticket is
  * done; `in` is read once at admission.  Returns BUSY if the queue is full,
- * OOM if the request alone exceeds the budget, INVALID on bad arguments.
+ * OOM if the request alone exceeds the budget, INVALID on bad arguments or a
+ * plan built on another device than the server's.
  */
 spider_status spider_submit(spider_server_t srv, spider_plan_t plan, const void* in, void* out,
                             int steps, uint64_t* ticket);

@@ -65,6 +65,7 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
 void set_tile2(spider_plan_s* p, int h);
 // Geometry of the plan's work units inside batched launches (from its current tile height).
 void set_batch_geometry(spider_plan_s* p);
+spider_status check_device(const spider_plan_s* p);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
 // Launches per replayed graph body of a long time loop (even); loops of more than
 // twice as many launches replay bodies instead of capturing the whole loop.

@@ -268,8 +268,13 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
   return SPIDER_OK;
 }
 
-static BatchArena& global_arena() {
-  static BatchArena* a = new BatchArena();  // lives until process exit
+// One descriptor arena per device (its buffers live on that device).
+static BatchArena& global_arena(int device) {
+  static std::mutex mu;
+  static std::map<int, BatchArena*> arenas;  // live until process exit
+  std::lock_guard<std::mutex> lk(mu);
+  BatchArena*& a = arenas[device];
+  if (!a) a = new BatchArena();
   return *a;
 }
 
@@ -432,6 +437,8 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
   std::vector<BatchItem> items;
   for (int i = 0; i < n; ++i) {
     if (!plans[i] || !ins[i] || !outs[i]) return fail(SPIDER_ERR_INVALID, "NULL plan or grid in batch entry %d", i);
+    spider_status dev_st = check_device(plans[i]);
+    if (dev_st != SPIDER_OK) return dev_st;
     for (int j = 0; j < i; ++j)
       if (plans[j] == plans[i])
         return fail(SPIDER_ERR_INVALID, "a plan appears twice in one batch (its scratch buffer is per plan)");
@@ -441,7 +448,7 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
     }
     items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
-  return enqueue_batch(global_arena(), items, static_cast<hipStream_t>(stream));
+  return enqueue_batch(global_arena(plans[0]->device), items, static_cast<hipStream_t>(stream));
 }
 
 spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue, spider_server_t* out) {
@@ -473,6 +480,9 @@ spider_status spider_submit(spider_server_t S, spider_plan_t plan, const void* i
       (plan->ndim == 2 ? plan->r > 3 : plan->r != 1) || plan->row_swap)
     return fail(SPIDER_ERR_UNSUPPORTED,
                 "the server runs 16-bit plans with the implicit row swap: 2-D radius 1..3, 3-D radius 1");
+  if (plan->device != S->device)
+    return fail(SPIDER_ERR_INVALID, "the plan was built on device %d, the server runs on device %d", plan->device,
+                S->device);
   const size_t fp = 2 * plan->grid_bytes;
   if (fp > S->budget) return fail(SPIDER_ERR_OOM, "request needs %zu bytes, budget is %zu", fp, S->budget);
   std::lock_guard<std::mutex> lk(S->mu);

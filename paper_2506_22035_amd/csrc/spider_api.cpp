@@ -114,6 +114,17 @@ static int auto_tile_h_direct(const spider_plan_s* p) {
   return std::min(p->ny, 64);
 }
 
+// Plans hold device memory of the device current at spider_plan; their work must
+// run there too.
+spider_status check_device(const spider_plan_s* p) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev != p->device)
+    return fail(SPIDER_ERR_INVALID, "the plan was built on device %d but device %d is current", p->device, dev);
+  return SPIDER_OK;
+}
+
 // The grid-sized scratch buffer is allocated on first use, so plans that only
 // feed the server (which owns per-request scratch) never hold one.
 spider_status ensure_scratch(spider_plan_s* p) {
@@ -622,6 +633,8 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
   if (!in || !out) return fail(SPIDER_ERR_INVALID, "in/out is NULL");
   if (steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  spider_status dev_st = check_device(p);
+  if (dev_st != SPIDER_OK) return dev_st;
   std::lock_guard<std::mutex> lk(p->mu);
   if (steps > 0) {
     spider_status st = ensure_scratch(p);
