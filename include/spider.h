@@ -85,7 +85,8 @@ typedef struct {
                        a 16-bit carry and radius <= 3 (else two where supported, else
                        one).  With 0 and autotune the plan also times the depths and
                        keeps the fastest per step.  A time loop of n steps runs n / T
-                       fused launches and then n mod T single steps.  The results agree
+                       fused launches, then (T > 2) one two-step launch for a
+                       remainder of two or three steps, then a single step for one.  The results agree
                        to rounding; on 1-D lines they are identical bit for bit, and see
                        band_height for 2-D. */
     int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16

@@ -39,14 +39,15 @@ struct spider_plan_s {
   int time_block = 1;                   // steps fused per launch of the matrix engines (1..4)
   int tile_h2 = 0;                      // segment height of the fused kernel
   spider_impl::BandGrid grid_tb2{};     // fused kernel: 240-wide strips (two steps) or pair_tb_width
+  spider_impl::BandGrid grid_rem2{};    // time_block > 2: two-step kernel for a remainder of 2 or 3 steps
   spider_impl::BandGrid grid_batch{};   // one-step kernel inside batched launches (taller segments)
   spider_impl::BandGrid grid_batch2{};  // two fused steps inside batched launches (paired bands)
   bool batch_fuse = false;              // grid_batch2 is set: batches advance this grid two steps per launch
   hipStream_t cap_stream = nullptr;
   std::map<std::tuple<const void*, const void*, int>, hipGraphExec_t> graphs;
-  // long time loops: one graph of kGraphBody launches of one kind (fused or single)
-  // between two buffers, replayed; keyed by (fused, first source, first destination)
-  std::map<std::tuple<bool, const void*, const void*>, hipGraphExec_t> body_graphs;
+  // long time loops: one graph of kGraphBody launches of one kind (steps per launch)
+  // between two buffers, replayed; keyed by (steps per launch, first source, first destination)
+  std::map<std::tuple<int, const void*, const void*>, hipGraphExec_t> body_graphs;
   std::mutex mu;
 };
 
@@ -70,7 +71,6 @@ spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int ste
 // Launches per replayed graph body of a long time loop (even); loops of more than
 // twice as many launches replay bodies instead of capturing the whole loop.
 constexpr int kGraphBody = 256;
-spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, int fused, int total, hipStream_t s);
 // Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).
 spider_status autotune_tile(spider_plan_s* p);
 }  // namespace spider_impl

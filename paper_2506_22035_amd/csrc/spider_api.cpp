@@ -266,9 +266,9 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
   return (int)h;
 }
 
-void set_time_block(spider_plan_s* p, int T, int tile_h) {
-  p->time_block = T;
-  if (T < 2) return;
+// grid_tb2 and tile_h2 for the plan's time_block (>= 2).
+static void set_fused_grid(spider_plan_s* p, int tile_h) {
+  const int T = p->time_block;
   p->grid_tb2 = p->grid_template;
   if (p->ndim != 1) {
     const int sw = T == 2 ? kStripW2_host : pair_tb_width(T, p->r);
@@ -277,27 +277,65 @@ void set_time_block(spider_plan_s* p, int T, int tile_h) {
   set_tile2(p, tile_h ? tile_h : auto_tile_h_tb2(p));
 }
 
-// Enqueue the whole time loop as fused launches of time_block steps, then single
-// steps for the remainder: buffers b_0 = in,
-// b_1 .. b_L (L launches) with b_L = out, alternating between out and the plan's
-// scratch so that the last launch lands in out and `in` is never written (unless
-// in == out).
-// The launches of a time loop of `steps` steps: `fused` of time_block steps, then
-// single steps; `total` in all.
-static void loop_launches(const spider_plan_s* p, int steps, int* fused, int* total) {
-  const int tb = p->time_block;
-  *fused = tb >= 2 ? steps / tb : 0;
-  *total = *fused + (steps - tb * *fused);
+void set_time_block(spider_plan_s* p, int T, int tile_h) {
+  p->time_block = T;
+  if (T < 2) return;
+  if (T > 2) {
+    // the two-step kernel (heuristic height) runs remainders of two or three steps
+    p->time_block = 2;
+    set_fused_grid(p, 0);
+    p->grid_rem2 = p->grid_tb2;
+    p->time_block = T;
+  }
+  set_fused_grid(p, tile_h);
 }
 
-// Launches k in [k0, k1] of a loop of `total` launches (`fused` of them fused),
-// reading `src` first.  Buffers b_k = out if (total - k) is even, else scratch.
-static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* out, int k0, int k1, int fused,
-                                      int total, hipStream_t s) {
+// Two fused steps on the remainder grid of a plan with time_block > 2.
+static spider_status launch_rem2(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
+  BandGrid g = p->grid_rem2;
+  g.in = src;
+  g.out = dst;
+  // time_block > 2 exists for 1-D lines and for paired-line bands with a 16-bit carry
+  hipError_t e = p->ndim == 1 ? launch_band1d_tbt(p->r, p->operand, p->engine, 2, g, s)
+                              : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SPIDER_OK;
+}
+
+// The time loop is enqueued as launches of time_block fused steps, then (time_block
+// > 2) two-step launches for a remainder of two or three steps, then single steps:
+// buffers b_0 = in, b_1 .. b_L (L launches) with b_L = out, alternating between out
+// and the plan's scratch so that the last launch lands in out and `in` is never
+// written (unless in == out).
+struct LoopShape {
+  int fused;  // launches of time_block steps: k = 1 .. fused
+  int two;    // then two-step launches: k = fused + 1 .. fused + two
+  int total;  // then single steps up to k = total
+  int kind(int k) const { return k <= fused ? 3 : (k <= fused + two ? 2 : 1); }
+  int run_end(int k) const { return k <= fused ? fused : (k <= fused + two ? fused + two : total); }
+};
+
+static LoopShape loop_launches(const spider_plan_s* p, int steps) {
+  LoopShape L;
+  const int tb = p->time_block;
+  L.fused = tb >= 2 ? steps / tb : 0;
+  const int rem = steps - (tb >= 2 ? tb * L.fused : 0);
+  L.two = tb > 2 ? rem / 2 : 0;
+  L.total = L.fused + L.two + (rem - 2 * L.two);
+  return L;
+}
+
+// Launches k in [k0, k1] of the loop `L`, reading `src` first.  Buffers b_k = out if
+// (L.total - k) is even, else scratch.
+static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* out, int k0, int k1,
+                                      const LoopShape& L, hipStream_t s) {
   for (int k = k0; k <= k1; ++k) {
-    void* dst = ((total - k) % 2 == 0) ? out : p->d_scratch;
+    void* dst = ((L.total - k) % 2 == 0) ? out : p->d_scratch;
     if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: launch %d reads and writes one buffer", k);
-    spider_status st = (k <= fused) ? launch_step2(p, src, dst, s) : launch_step(p, src, dst, s);
+    const int kind = L.kind(k);
+    spider_status st = kind == 3   ? launch_step2(p, src, dst, s)
+                       : kind == 2 ? launch_rem2(p, src, dst, s)
+                                   : launch_step(p, src, dst, s);
     if (st != SPIDER_OK) return st;
     src = dst;
   }
@@ -325,12 +363,11 @@ spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int ste
     }
     return SPIDER_OK;
   }
-  int fused, total;
-  loop_launches(p, steps, &fused, &total);
+  const LoopShape L = loop_launches(p, steps);
   const void* src;
-  spider_status st = first_source(p, in, out, total, s, &src);
+  spider_status st = first_source(p, in, out, L.total, s, &src);
   if (st != SPIDER_OK) return st;
-  return enqueue_launches(p, src, out, 1, total, fused, total, s);
+  return enqueue_launches(p, src, out, 1, L.total, L, s);
 }
 
 // Capture the launches enqueued by `body` on the plan's capture stream as one
@@ -358,19 +395,20 @@ static spider_status capture(spider_plan_s* p, F body, hipGraphExec_t* exec) {
 }
 
 // A time loop of more than 2 kGraphBody launches: launch 1 directly, then every
-// whole body of kGraphBody launches of one kind (fused, then single) as a replay
-// of one cached graph, the rest directly.  kGraphBody is even, so a body leaves
-// its result in the buffer it started from and one graph serves every body
-// between the same two buffers.
-spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, int fused, int total, hipStream_t s) {
+// whole body of kGraphBody launches of one kind (steps per launch) as a replay of
+// one cached graph, the rest directly.  kGraphBody is even, so a body leaves its
+// result in the buffer it started from and one graph serves every body between
+// the same two buffers.
+static spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, const LoopShape& L, hipStream_t s) {
   static_assert(kGraphBody % 2 == 0, "a body must return to its first source");
+  const int total = L.total;
   const void* src;
   spider_status st = first_source(p, in, out, total, s, &src);
-  if (st == SPIDER_OK) st = enqueue_launches(p, src, out, 1, 1, fused, total, s);
+  if (st == SPIDER_OK) st = enqueue_launches(p, src, out, 1, 1, L, s);
   int k = 2;
   while (st == SPIDER_OK && k <= total) {
-    const bool kind = k <= fused;
-    const int run_end = kind ? fused : total;  // last launch of this kind
+    const int kind = L.kind(k);
+    const int run_end = L.run_end(k);  // last launch of this kind
     while (st == SPIDER_OK && run_end - k + 1 >= kGraphBody) {
       const void* from = ((total - (k - 1)) % 2 == 0) ? out : p->d_scratch;
       void* to = ((total - k) % 2 == 0) ? out : p->d_scratch;
@@ -380,7 +418,7 @@ spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, int fuse
         hipGraphExec_t exec = nullptr;
         // launches k .. k + kGraphBody - 1 of this loop: the same for every body
         st = capture(p, [&](hipStream_t cs) {
-          return enqueue_launches(p, from, out, k, k + kGraphBody - 1, fused, total, cs);
+          return enqueue_launches(p, from, out, k, k + kGraphBody - 1, L, cs);
         }, &exec);
         if (st != SPIDER_OK) return st;
         if (p->body_graphs.size() >= 16) {  // bound the cache (rare: waits for queued work first)
@@ -396,7 +434,7 @@ spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, int fuse
     }
     if (st == SPIDER_OK && k <= run_end) {
       const void* from = ((total - (k - 1)) % 2 == 0) ? out : p->d_scratch;
-      st = enqueue_launches(p, from, out, k, run_end, fused, total, s);
+      st = enqueue_launches(p, from, out, k, run_end, L, s);
       k = run_end + 1;
     }
   }
@@ -641,9 +679,8 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
     if (st != SPIDER_OK) return st;
   }
   if (!p->use_graph || steps < 2) return enqueue_steps(p, in, out, steps, s);
-  int fused, total;
-  loop_launches(p, steps, &fused, &total);
-  if (total > 2 * kGraphBody) return enqueue_long(p, in, out, fused, total, s);
+  const LoopShape L = loop_launches(p, steps);
+  if (L.total > 2 * kGraphBody) return enqueue_long(p, in, out, L, s);
   // Replay a graph of the whole time loop, captured once per (in, out, steps).
   auto key = std::make_tuple(in, (const void*)out, steps);
   auto it = p->graphs.find(key);

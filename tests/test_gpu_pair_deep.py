@@ -60,7 +60,8 @@ def test_fused_integer_exact(oracle_mod, T, engine, shape):
 @pytest.mark.parametrize("T", [3, 4])
 @pytest.mark.parametrize("steps", [1, 5, 7, 9])
 def test_steps_not_multiple_of_T(oracle_mod, T, steps):
-    # n steps run n // T fused launches and then n % T single steps
+    # n steps run n // T fused launches, then a two-step launch for a remainder of
+    # two or three, then a single step if one is left
     shape = (131, 300)
     w = sparse_int_taps(2, 9)
     x = si.grid_integer(shape, -1, 1, 11)
@@ -97,9 +98,11 @@ def test_even_radius_identical_to_single_steps(T):
     w /= w.sum()
     shape = (203, 517)
     xd, _ = to_dev(rng.uniform(0, 1, shape), "f16")
-    a = run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=T), xd, 2 * T)
-    b = run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=1), xd, 2 * T)
-    assert np.array_equal(a, b)
+    # 2T + 2 and 2T + 3 end with a two-step launch (and a single step)
+    for steps in (2 * T, 2 * T + 2, 2 * T + 3):
+        a = run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=T), xd, steps)
+        b = run(sp.Plan(w, shape, carry="f16", band_height=8, time_block=1), xd, steps)
+        assert np.array_equal(a, b), steps
 
 
 @pytest.mark.parametrize("T", [3, 4])
