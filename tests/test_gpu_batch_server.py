@@ -176,3 +176,45 @@ def test_server_queue_full_and_close():
     assert got_busy
     srv.close()  # admitted requests finish, queued ones fail with CLOSED
     torch.cuda.synchronize()
+
+
+def test_server_zero_steps_in_place_and_threads():
+    # zero-step requests copy, in-place requests (in == out) work, and submissions
+    # from several host threads at once all complete with their own results
+    import threading
+    import torch
+    mix = _mix()
+    srv = sp.Server(hbm_budget_bytes=1 << 30, max_slots=8)
+    try:
+        jobs = []   # (mix index, steps, in_place)
+        for k in range(len(mix)):
+            jobs += [(k, 0, False), (k, 4, True), (k, 9, False)]
+        plans = [sp.Plan(mix[k][0]["coeffs"], mix[k][0]["shape"], carry="f16") for k, _, _ in jobs]
+        ins = [mix[k][1].clone() for k, _, _ in jobs]
+        outs = [x if ip else torch.empty_like(x) for x, (_, _, ip) in zip(ins, jobs)]
+        torch.cuda.synchronize()
+        tickets = [None] * len(jobs)
+        errors = []
+
+        def submit(idx):
+            try:
+                for i in idx:
+                    tickets[i] = srv.submit(plans[i], ins[i], outs[i], jobs[i][1])
+            except Exception as e:   # reported below
+                errors.append(e)
+
+        threads = [threading.Thread(target=submit, args=(range(t, len(jobs), 4),)) for t in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        assert not errors, errors
+        assert len(set(tickets)) == len(jobs)
+        res = _wait(srv, tickets)
+        assert all(v == 0 for v in res.values())
+        for (k, st, ip), o in zip(jobs, outs):
+            wl, xd, _ = mix[k]
+            want = from_dev(xd) if st == 0 else _alone(wl, xd, st)
+            assert np.array_equal(from_dev(o), want), (k, st, ip)
+    finally:
+        srv.close()
