@@ -80,11 +80,11 @@ constexpr int pair_tb_width(int T, int r) {
 hipError_t launch_band2d_pair_tbt(int r, int operand, int engine, int T, const BandGrid& g, hipStream_t s);
 int band2d_pair_tbt_blocks_per_cu(int r, int operand, int engine, int T);
 // Paired-line bands on fp32 grids: 16-bit operands split from the fp32 values
-// (x_hi, and x_lo when `xlo`); one step (256-column strips) or two fused steps
-// (`fused`, 240 stored columns per strip).
-hipError_t launch_band2d_pair_f32(int r, int operand, int engine, bool xlo, bool fused, const BandGrid& g,
+// (x_hi, and x_lo when `xlo`); T steps per launch: one (256-column strips), two
+// (240 stored columns per strip) or three (pair_tb_width(3, r); sparse engine).
+hipError_t launch_band2d_pair_f32(int r, int operand, int engine, bool xlo, int T, const BandGrid& g,
                                   hipStream_t s);
-int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, bool fused);
+int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, int T);
 
 // 1-D band engine: the line is cut into nstrips = ceil((nx + 8) / 256) blocks of 256
 // outputs at x0 = 256 j - 8; each wave streams seg_h consecutive blocks (nblocks =

@@ -61,7 +61,7 @@ static int auto_tile_h_2d(const spider_plan_s* p) {
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
   int per_cu = p->band_h == 8 && p->carry == SPIDER_F32
-                   ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, false)
+                   ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, 1)
                : p->band_h == 8        ? band2d_pair_blocks_per_cu(p->r, p->operand, p->engine)
                : p->carry == SPIDER_F32 ? band2d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3)
                                         : band2d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0);
@@ -152,7 +152,7 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
     BandGrid g = p->grid_template;
     g.in = src;
     g.out = dst;
-    e = p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, false, g, s)
+    e = p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, 1, g, s)
                                : launch_band2d_pair(p->r, p->operand, p->engine, g, s);
   } else if (p->ndim == 2 && p->carry == SPIDER_F32) {
     BandGrid g = p->grid_template;
@@ -179,11 +179,13 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   BandGrid g = p->grid_tb2;
   g.in = src;
   g.out = dst;
-  hipError_t e = p->ndim == 1 ? launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
-                 : p->time_block > 2 ? launch_band2d_pair_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
-                 : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
-                 : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, true, g, s)
-                                          : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
+  hipError_t e =
+      p->ndim == 1 ? launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+      : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
+      : p->carry == SPIDER_F32
+          ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, p->time_block, g, s)
+      : p->time_block > 2 ? launch_band2d_pair_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+                          : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SPIDER_OK;
 }
@@ -252,10 +254,11 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
     const long long h = (nblk + 12LL * ncu - 1) / (12LL * ncu);
     return (int)std::min<long long>(std::max<long long>(h, 16), nblk);
   }
-  int per_cu = p->time_block > 2 ? band2d_pair_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->time_block)
-               : p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
-               : p->carry == SPIDER_F32 ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, true)
-                                        : band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine);
+  int per_cu = p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
+               : p->carry == SPIDER_F32
+                   ? band2d_pair_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, p->time_block)
+               : p->time_block > 2 ? band2d_pair_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->time_block)
+                                   : band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
   const long long nstrips = p->grid_tb2.nstrips;
@@ -295,9 +298,11 @@ static spider_status launch_rem2(spider_plan_s* p, const void* src, void* dst, h
   BandGrid g = p->grid_rem2;
   g.in = src;
   g.out = dst;
-  // time_block > 2 exists for 1-D lines and for paired-line bands with a 16-bit carry
-  hipError_t e = p->ndim == 1 ? launch_band1d_tbt(p->r, p->operand, p->engine, 2, g, s)
-                              : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
+  // time_block > 2 exists for 1-D lines and for paired-line bands (16-bit carry, or
+  // fp32 carry on the sparse engine)
+  hipError_t e = p->ndim == 1             ? launch_band1d_tbt(p->r, p->operand, p->engine, 2, g, s)
+                 : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, 2, g, s)
+                                          : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SPIDER_OK;
 }
@@ -636,11 +641,12 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     // two fused steps per launch: 2-D, radius <= 3, 16-bit carry
     const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair) && !p->row_swap;
     // three or four: paired-line bands with a 16-bit carry (the dense engine
-    // measured slower at four)
-    const bool tbt_ok = tb2_ok && pair && low;
+    // measured slower at four); three with an fp32 carry on the sparse engine
+    const bool f32_tbt = pair && o.carry == SPIDER_F32 && engine == SPIDER_ENGINE_SPARSE;
+    const bool tbt_ok = tb2_ok && pair && (low || f32_tbt);
     // 1-D lines: two to four steps on the 16-point band engine (16-bit carry, r <= 3)
     const bool tb1_ok = ndim == 1 && radius <= 3 && low && !p->row_swap;
-    p->max_time_block = tb1_ok ? 4 : !tb2_ok ? 1 : !tbt_ok ? 2 : (engine == SPIDER_ENGINE_DENSE ? 3 : 4);
+    p->max_time_block = tb1_ok ? 4 : !tb2_ok ? 1 : !tbt_ok ? 2 : (engine == SPIDER_ENGINE_DENSE || f32_tbt ? 3 : 4);
     int T;
     if (o.time_block == 0) {
       // deeper fusion pays on large grids; small ones lack waves to hide its longer pipeline

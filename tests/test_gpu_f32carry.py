@@ -73,7 +73,7 @@ def test_f32_carry_rounded_equals_16bit_carry(operand, engine, band):
     wl = si.workload("box2d49p_10240", small=True)
     x16, _ = to_dev(wl["make_grid"](), operand)
     x32 = x16.to(torch.float32)
-    for tb in (1, 2):
+    for tb in ((1, 2, 3) if (engine == "sparse" and band == 8) else (1, 2)):
         p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, engine=engine, time_block=tb, band_height=band)
         y16 = torch.empty_like(x16)
         p16.apply(x16, y16, 9)
@@ -81,6 +81,8 @@ def test_f32_carry_rounded_equals_16bit_carry(operand, engine, band):
         p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine=engine, split=2, operand=operand,
                       band_height=band, time_block=tb if band == 8 else 1)
         y32 = torch.empty_like(x32)
+        if band == 8:   # (16-point bands fuse bit-identically to single steps)
+            assert p32.info()["time_block"] == p16.info()["time_block"]
         p32.apply(x32, y32, 9)
         torch.cuda.synchronize()
         assert torch.equal(y32.to(x16.dtype), y16), tb
@@ -167,3 +169,50 @@ def test_batch_and_server_reject_f32_carry():
         srv.submit(plan, x, y, 2)
     assert e.value.status == 2
     srv.close()
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES + [(131, 700), (64, 233)])
+def test_three_steps_integer_exact(oracle_mod, operand, shape):
+    # three fused steps on the sparse engine; step counts that three does not divide
+    # end with a two-step launch and a single step
+    cases = [(np.ones((3, 3)), 5, (1, 2))]
+    cases += [(si.integer_coeffs(2, r, -1, 1, 90 + r, kind), steps, (-2, 2))
+              for kind, r, steps in [("box", 1, 4), ("star", 3, 3), ("box", 3, 3), ("box", 2, 5)]]
+    for w, steps, (lo, hi) in cases:
+        x = si.grid_integer(shape, lo, hi, 70 + shape[1])
+        xd, x64 = to_dev(x, "f32")
+        plan = sp.Plan(w, shape, carry="f32", engine="sparse", split=3, operand=operand, band_height=8,
+                       time_block=3)
+        assert plan.info()["time_block"] == 3
+        ref = oracle_mod.apply(w, x64, steps)
+        assert np.abs(oracle_mod.apply(w, x64, steps - 1)).max() < 65504
+        got = run(plan, xd, steps)
+        assert np.array_equal(got, ref), (w.shape, steps, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+@pytest.mark.parametrize("name", ["box2d49p_10240", "star2d13p_8192"])
+def test_three_steps_tolerance_tiles_and_aliasing(oracle_mod, operand, name):
+    import torch
+    wl = si.workload(name, small=True)
+    xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
+    ref = oracle_mod.apply(wl["coeffs"], x64, wl["steps"])
+    res = []
+    for th in (0, 2, 31, 64, 1000):
+        plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, operand=operand,
+                       time_block=3, tile_h=th)
+        res.append(run(plan, xd, wl["steps"]))
+    for r_ in res[1:]:
+        assert np.array_equal(r_, res[0])
+    rms, mx = rel_errors(res[0], ref)
+    print("%s f32 carry, %s operands, three steps: rel-RMS %.3e rel-max %.3e" % (name, operand, rms, mx))
+    tr, tm = TOL3[operand]
+    assert rms <= tr and mx <= tm
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, operand=operand, time_block=3)
+    keep = xd.clone()
+    for steps in (3, 4, 5, 6):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), run(plan, xd, steps)), steps
+    assert torch.equal(xd, keep)

@@ -126,10 +126,13 @@ def test_fused_tile_heights_agree_and_aliasing(T):
 
 
 def test_unsupported_depths_fall_back():
-    # 3 or 4 need paired-line bands and a 16-bit carry; otherwise two where supported, else one
+    # 3 or 4 need paired-line bands (an fp32 carry: three, on the sparse engine);
+    # otherwise two where supported, else one
     w = np.ones((3, 3)) / 9
     assert sp.Plan(w, (64, 64), carry="f16", band_height=16, time_block=4).info()["time_block"] == 2
-    assert sp.Plan(w, (64, 64), carry="f32", engine="sparse", split=3, time_block=3).info()["time_block"] == 2
+    assert sp.Plan(w, (64, 64), carry="f32", engine="sparse", split=3, time_block=4).info()["time_block"] == 3
+    assert sp.Plan(w, (64, 64), carry="f32", engine="dense", split=3, time_block=3).info()["time_block"] == 2
+    assert sp.Plan(w, (64, 64), carry="f32", engine="sparse", band_height=16, time_block=3).info()["time_block"] == 1
     w4 = np.ones((9, 9)) / 81
     assert sp.Plan(w4, (64, 64), carry="f16", time_block=4).info()["time_block"] == 1
 
