@@ -32,7 +32,7 @@ METRIC = "GStencil/s at stated error vs FP64 oracle (vs plain GPU path); p50/p99
 TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": (5e-5, 5e-5)}
 KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band_pair.hip", "paper_2506_22035_amd/csrc/band_pair.h",
                   "paper_2506_22035_amd/csrc/band_common.h"]
-# the dominant kernel of the headline run: two fused time steps per launch
+# the dominant kernel of the headline run: four fused time steps per launch
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_pair_tbt_box49p_f16_10240_traffic.json")
 
 
@@ -428,8 +428,12 @@ def main():
                           "p99": round(float(np.percentile(per, 99)), 4)},
            "roofline": roof}
 
-    if not headline:
+    # errors, the plain fp32 path, the fp32-carry mode and the engine ablation run on
+    # every 2-D workload with a 16-bit carry; the serving sample and the host
+    # baseline on the headline workload only
+    if not (len(shape) == 2 and args.carry in ("f16", "bf16")):
         args.no_extras = True
+    if not headline:
         args.no_cpu_baseline = True
 
     if not args.no_extras:
@@ -493,7 +497,7 @@ def main():
             pa.close()
         out["ablation_gstencil_s"] = abl
 
-    if not args.no_extras:
+    if not args.no_extras and headline:
         # a short serving sample (the full sweep is `bench.py --serving`)
         out["serving_sample"] = serving(torch, sp, si, 200, [0.75])
 

@@ -29,6 +29,7 @@ struct spider_plan_s {
   int nrows = 0;          // kernel rows (lines of taps along x)
   uint32_t rowmask = 0;   // rows with a non-zero tap
   bool has_zero_tap = false;
+  bool star = false;  // direct engine: every non-zero tap on an axis through the centre
   void* d_apack = nullptr;
   void* d_ipack = nullptr;
   void* d_dpack = nullptr;

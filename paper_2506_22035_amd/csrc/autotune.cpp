@@ -21,7 +21,7 @@
 namespace spider_impl {
 
 namespace {
-using Key = std::tuple<int, int, int, int, int, int, int, uint32_t, bool>;
+using Key = std::tuple<int, int, int, int, int, int, int, uint32_t, int>;
 std::mutex g_mu;
 std::map<Key, int> g_cache;
 std::map<Key, int> g_cache2;  // fused kernel
@@ -30,7 +30,7 @@ std::map<Key, int> g_cacheT;  // fused steps per launch chosen by the depth sear
 Key key_of(const spider_plan_s* p) {
   return Key(p->ndim, p->nz, p->ny, p->nx, p->r, p->carry * 8 + p->operand, p->engine * 8 + p->split + 64 * p->band_h + 4096 * p->row_swap + 8192 * p->time_block,
              p->rowmask,
-             p->has_zero_tap);
+             (int)p->has_zero_tap + 2 * (int)p->star);
 }
 
 void set_tile(spider_plan_s* p, int h) {

@@ -121,9 +121,10 @@ hipError_t launch_band_batch(int operand, int engine, int cls, const BandGrid* g
 constexpr int kRowsY3 = 4;
 
 // Plain direct-sum engine (fp32 / fp64 carry).  coeffs_dev holds (2r+1)^ndim
-// taps in the carry dtype.  dtype: 0 = f64, 1 = f32.  skip_zero_taps selects the
-// variant that branches over zero taps (star shapes) instead of multiplying them.
-hipError_t launch_direct(int ndim, int r, int dtype, bool skip_zero_taps, const void* in, void* out, int nz, int ny,
+// taps in the carry dtype.  dtype: 0 = f64, 1 = f32.  zero_taps: 0 = multiply every
+// tap, 1 = branch over zero taps at run time, 2 = star stencil (every non-zero tap
+// on an axis through the centre): only those taps are compiled in.
+hipError_t launch_direct(int ndim, int r, int dtype, int zero_taps, const void* in, void* out, int nz, int ny,
                          int nx, const void* coeffs_dev, int seg_h, hipStream_t s);
 
 // Outputs per 2-D band wave strip; strip s covers x in [256 s - 8, 256 s + 248),

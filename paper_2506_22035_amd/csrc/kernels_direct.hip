@@ -143,7 +143,10 @@ __device__ __forceinline__ void store_out4(__amdgpu_buffer_rsrc_t rs, int x0, in
 // feeds it through kernel row a = 2R - m.  After line j, acc[0] is complete and the
 // window shifts by one line.  Lines are staged two ahead.
 
-template <typename T, int R, bool SKIPZ>
+// ZM (zero taps): 0 = every tap is multiplied, 1 = zero taps are skipped at run
+// time, 2 = star stencil: only taps on the axes through the centre exist (fixed
+// when the kernel is compiled, so the others cost nothing).
+template <typename T, int R, int ZM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 : 2))) void direct2d_kernel(
     const T* __restrict__ in, T* __restrict__ out, int ny, int nx, const T* __restrict__ w, int seg_h, int nstrips) {
   using L = Line<T, R>;
@@ -188,8 +191,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
         const int a = 2 * R - m;
 #pragma unroll
         for (int t = 0; t < RR; ++t) {
+          if (ZM == 2 && a != R && t != R) continue;  // folded away once the loops unroll
           const T c = w[a * RR + t];
-          if (!SKIPZ || c != T(0)) {
+          if (ZM != 1 || c != T(0)) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[m][k] = fma_t<T>(c, v[k + t - R + L::LEAD], acc[m][k]);
           }
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(R <= 4 ? 4 :
 // streams input planes (kRowsY3 + 2R lines each), staged one plane ahead.
 // acc[m][b] holds output line (plane p - 2R + m, y = yb0 + b) while plane p is applied.
 
-template <typename T, int R, bool SKIPZ>
+template <typename T, int R, int ZM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && R >= 2) ? 1 : 2))) void direct3d_kernel(
     const T* __restrict__ in, T* __restrict__ out, int nz, int ny, int nx, const T* __restrict__ w, int seg_h,
     int nstrips, int nsegy) {
@@ -270,8 +274,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
           if (dy < 0 || dy >= RR) continue;
 #pragma unroll
           for (int t = 0; t < RR; ++t) {
+            // star: at most one of dz, dy, dx off the centre
+            if (ZM == 2 && (dz != R) + (dy != R) + (t != R) > 1) continue;
             const T c = w[(dz * RR + dy) * RR + t];
-            if (!SKIPZ || c != T(0)) {
+            if (ZM != 1 || c != T(0)) {
 #pragma unroll
               for (int k = 0; k < 4; ++k) acc[m][b][k] = fma_t<T>(c, v[k + t - R + L::LEAD], acc[m][b][k]);
             }
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(256) void direct1d_kernel(const T* __restrict__ in,
   }
 }
 
-template <typename T, bool SKIPZ>
+template <typename T, int ZM>
 static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, int nz, int ny, int nx,
                                   const void* w, int seg_h, hipStream_t s) {
   const int sw = 256 - 2 * 4 * ((r + 3) / 4);
@@ -358,7 +364,7 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
     const dim3 grid(nstrips * nseg), block(64);
     switch (r) {
 #define SPIDER_D2(RV) \
-  case RV: hipLaunchKernelGGL((direct2d_kernel<T, RV, SKIPZ>), grid, block, 0, s, pin, pout, ny, nx, pw, seg_h, nstrips); break;
+  case RV: hipLaunchKernelGGL((direct2d_kernel<T, RV, ZM>), grid, block, 0, s, pin, pout, ny, nx, pw, seg_h, nstrips); break;
       SPIDER_D2(1) SPIDER_D2(2) SPIDER_D2(3) SPIDER_D2(4) SPIDER_D2(5) SPIDER_D2(6) SPIDER_D2(7)
 #undef SPIDER_D2
       default: return hipErrorInvalidValue;
@@ -370,7 +376,7 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
     switch (r) {
 #define SPIDER_D3(RV)                                                                                                \
   case RV:                                                                                                           \
-    hipLaunchKernelGGL((direct3d_kernel<T, RV, SKIPZ>), grid, block, 0, s, pin, pout, nz, ny, nx, pw, seg_h, nstrips, nsegy); \
+    hipLaunchKernelGGL((direct3d_kernel<T, RV, ZM>), grid, block, 0, s, pin, pout, nz, ny, nx, pw, seg_h, nstrips, nsegy); \
     break;
       SPIDER_D3(1) SPIDER_D3(2)
 #undef SPIDER_D3
@@ -380,14 +386,21 @@ static hipError_t direct_dispatch(int ndim, int r, const void* in, void* out, in
   return hipGetLastError();
 }
 
-hipError_t launch_direct(int ndim, int r, int dtype, bool skip_zero_taps, const void* in, void* out, int nz, int ny,
+template <typename T>
+static hipError_t direct_zm(int zmode, int ndim, int r, const void* in, void* out, int nz, int ny, int nx,
+                            const void* w, int seg_h, hipStream_t s) {
+  switch (zmode) {
+    case 0: return direct_dispatch<T, 0>(ndim, r, in, out, nz, ny, nx, w, seg_h, s);
+    case 1: return direct_dispatch<T, 1>(ndim, r, in, out, nz, ny, nx, w, seg_h, s);
+    case 2: return direct_dispatch<T, 2>(ndim, r, in, out, nz, ny, nx, w, seg_h, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_direct(int ndim, int r, int dtype, int zero_taps, const void* in, void* out, int nz, int ny,
                          int nx, const void* coeffs_dev, int seg_h, hipStream_t s) {
-  if (dtype == 0)
-    return skip_zero_taps ? direct_dispatch<double, true>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s)
-                          : direct_dispatch<double, false>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
-  if (dtype == 1)
-    return skip_zero_taps ? direct_dispatch<float, true>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s)
-                          : direct_dispatch<float, false>(ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
+  if (dtype == 0) return direct_zm<double>(zero_taps, ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
+  if (dtype == 1) return direct_zm<float>(zero_taps, ndim, r, in, out, nz, ny, nx, coeffs_dev, seg_h, s);
   return hipErrorInvalidValue;
 }
 

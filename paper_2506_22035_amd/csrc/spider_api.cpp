@@ -141,7 +141,8 @@ spider_status ensure_scratch(spider_plan_s* p) {
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
   hipError_t e;
   if (p->engine == SPIDER_ENGINE_DIRECT) {
-    e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, p->has_zero_tap, src, dst, p->nz, p->ny, p->nx,
+    e = launch_direct(p->ndim, p->r, p->carry == SPIDER_F64 ? 0 : 1, p->star ? 2 : (p->has_zero_tap ? 1 : 0), src,
+                      dst, p->nz, p->ny, p->nx,
                       p->d_coeffs, p->tile_h, s);
   } else if (p->ndim == 1) {
     BandGrid g = p->grid_template;
@@ -571,6 +572,13 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     p->nrows = ndim == 1 ? 1 : (ndim == 2 ? kw : kw * kw);
     p->has_zero_tap = false;
     for (double c : p->coeffs) p->has_zero_tap |= (c == 0.0);
+    // star: no non-zero tap with more than one offset coordinate away from the centre
+    p->star = ndim >= 2;
+    for (int i = 0; i < ncoef; ++i) {
+      int off = 0;
+      for (int d = 0, q = i; d < ndim; ++d, q /= kw) off += (q % kw) != radius;
+      if (off > 1 && p->coeffs[i] != 0.0) p->star = false;
+    }
     p->tile_h = o.tile_h ? o.tile_h : auto_tile_h_direct(p);
   } else {
     // Offline transformation, one kernel row (line of taps along x) at a time, or
@@ -638,7 +646,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     }
     g.nblocks = ndim == 1 ? g.nsegs_y : g.nstrips * g.nsegs_y * g.nsegs_z;
     set_batch_geometry(p);
-    // two fused steps per launch: 2-D, radius <= 3, 16-bit carry
+    // two fused steps per launch: 2-D, radius <= 3, a 16-bit carry or paired-line bands
     const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair) && !p->row_swap;
     // three or four: paired-line bands with a 16-bit carry (the dense engine
     // measured slower at four); three with an fp32 carry on the sparse engine

@@ -119,6 +119,28 @@ def test_direct_random(oracle_mod, carry, shape, r):
     assert rms <= TOL[(carry, 0)][0] and mx <= TOL[(carry, 0)][1]
 
 
+@pytest.mark.parametrize("carry", ["f32", "f64"])
+def test_direct_star_and_sparse_taps_integer_exact(oracle_mod, carry):
+    # the direct engine compiles only the axis taps of star stencils, branches over zero
+    # taps of other sparse stencils and multiplies every tap of full ones: all exact
+    rng = np.random.default_rng(17)
+    cases = [(2, r, kind) for r in (1, 2, 3, 5, 7) for kind in ("star", "box")] + \
+            [(3, r, kind) for r in (1, 2) for kind in ("star", "box")]
+    for ndim, r, kind in cases:
+        w = si.integer_coeffs(ndim, r, -2, 2, 300 + 10 * r + ndim, kind)
+        w[(r,) * ndim] = 1.0
+        if kind == "star":
+            w[(r,) * (ndim - 1) + (0,)] = 0.0   # a zero tap on an axis as well
+        else:
+            w[(0,) * ndim] = 0.0                # one zero tap off the axes: run-time skipping
+        shape = (37, 300) if ndim == 2 else (9, 20, 70)
+        xd, x64 = to_dev(rng.integers(-3, 4, shape).astype(np.float64), carry)
+        plan = sp.Plan(w, shape, carry=carry)
+        assert plan.info()["engine"] == "direct"
+        got = run(plan, xd, 2)
+        assert np.array_equal(got, oracle_mod.apply(w, x64, 2)), (ndim, r, kind)
+
+
 @pytest.mark.parametrize("carry", ["f16", "f32"])
 @pytest.mark.parametrize("steps", [0, 1, 2, 3, 4])
 def test_aliasing_and_step_counts(oracle_mod, carry, steps):
