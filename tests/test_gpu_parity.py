@@ -204,6 +204,29 @@ def test_long_loops_replay_bodies(oracle_mod, T):
     assert rms <= 5e-3 and mx <= 1e-2, (rms, mx)
 
 
+def test_two_plans_on_two_streams():
+    # one plan per stream may run concurrently (each owns its scratch); results must
+    # equal the same applies run one after the other
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    xd, _ = to_dev(wl["make_grid"](), "f16")
+    wl2 = si.workload("star2d13p_8192", small=True)
+    xd2, _ = to_dev(wl2["make_grid"](), "f16")
+    ref1 = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f16"), xd, 13)
+    ref2 = run(sp.Plan(wl2["coeffs"], wl2["shape"], carry="f16"), xd2, 11)
+    p1 = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+    p2 = sp.Plan(wl2["coeffs"], wl2["shape"], carry="f16")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y1, y2 = torch.empty_like(xd), torch.empty_like(xd2)
+        p1.apply(xd, y1, 13, stream=s1)
+        p2.apply(xd2, y2, 11, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(y1), ref1)
+        assert np.array_equal(from_dev(y2), ref2)
+
+
 def test_tile_heights_agree():
     import torch
     wl = si.workload("star2d13p_8192", small=True)
