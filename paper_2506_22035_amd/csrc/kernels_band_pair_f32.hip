@@ -286,15 +286,14 @@ __device__ __forceinline__ void band2d_pair_f32_body12(const BandGrid& g, int w,
 // single step stays within the 4-wave budget.)
 template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T>
 __device__ __forceinline__ void band2d_pair_f32_bodyT(const BandGrid& g, int w, uint32_t* lds) {
-  constexpr bool FUSED = T > 1;
+  static_assert(T >= 3, "one and two steps use band2d_pair_f32_body12");
   constexpr int NP = R + 1;
   constexpr int UP = (NP >= 3) ? NP : 2 * NP;
   constexpr int NLP = XLO ? 2 : 1;             // 16-bit LDS lines per input line (hi, lo)
   constexpr int LINE = kPairRowDw;
   constexpr int PAIRSZ = 2 * NLP * LINE;       // one staged line pair (hi/lo)
   // stored strip width and the columns computed left of it (4 mod 8)
-  constexpr int W = T == 1 ? kStripWPair : (T == 2 ? kStripWPair2 : pair_tb_width(T, R));
-  constexpr int MRG = T <= 2 ? kPairWinLead : pair_tb_margin(T, R);
+  constexpr int W = pair_tb_width(T, R), MRG = pair_tb_margin(T, R);
   const int lane = threadIdx.x;
   const int strip = w % g.nstrips, seg = w / g.nstrips;
   const int xp = strip * W - MRG;
@@ -332,8 +331,7 @@ __device__ __forceinline__ void band2d_pair_f32_bodyT(const BandGrid& g, int w, 
   const int xo = xp + 8 * (lane & 15) + 4 * ((lane >> 4) & 1);
   const int phi = lane >> 5;
   const int line_off = phi * nx;
-  const int x_lo = FUSED ? strip * W : 0;
-  const int x_hi = FUSED ? min(nx, x_lo + W) : nx;
+  const int x_lo = strip * W, x_hi = min(nx, x_lo + W);  // stored columns
   uint32_t ova[4], ovb[4];
   uint32_t ma[4], mb[4];  // intermediate values inside the grid (fused only)
 #pragma unroll
@@ -349,9 +347,7 @@ __device__ __forceinline__ void band2d_pair_f32_bodyT(const BandGrid& g, int w, 
   uint32_t* mid = lds + 2 * PAIRSZ;                     // levels 1 .. T-1: 2 slots x PAIRSZ each
   // intermediate values: lane's 2 dwords of half a at data dword 4n + 2 + 2 (h & 1) of line phi
   const int mwo = 6 * (lane & 15) + (((lane >> 4) & 1) ? 6 : 2) + phi * LINE;
-  if constexpr (FUSED) {
-    for (int i = lane; i < 2 * (T - 1) * PAIRSZ; i += 64) mid[i] = 0u;
-  }
+  for (int i = lane; i < 2 * (T - 1) * PAIRSZ; i += 64) mid[i] = 0u;
 
   const int yin0 = y0 - T * R;
   LineWalk lin(g.in, yin0, max(0, yin0), min(ny, y0 + hrows + T * R), nx * 4);
