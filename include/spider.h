@@ -199,8 +199,9 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
  * current HIP device.  Requests are admitted while their device footprint
  * (two grid-sized buffers of the plan's carry dtype) fits in `hbm_budget_bytes`
  * and a slot is free (max_slots); admitted requests share every round's
- * batched launch, and a request that arrives while others run joins at the
- * next round.  Grid state stays on the device between rounds.
+ * batched launch (2-D grids whose plan fuses three or four steps run their own
+ * fused launches in the round instead), and a request that arrives while others
+ * run joins at the next round.  Grid state stays on the device between rounds.
  */
 spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue,
                                    spider_server_t* out);

@@ -69,6 +69,10 @@ void set_tile2(spider_plan_s* p, int h);
 void set_batch_geometry(spider_plan_s* p);
 spider_status check_device(const spider_plan_s* p);
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s);
+// The same loop with a caller-owned grid-sized scratch buffer in place of the plan's
+// (the server gives every request its own, so requests may share a plan).
+spider_status enqueue_steps_scratch(spider_plan_s* p, const void* in, void* out, void* scratch, int steps,
+                                    hipStream_t s);
 // Launches per replayed graph body of a long time loop (even); loops of more than
 // twice as many launches replay bodies instead of capturing the whole loop.
 constexpr int kGraphBody = 256;

@@ -392,13 +392,19 @@ void server_loop(spider_server_s* S) {
       continue;
     }
     // one round: every admitted request advances by up to round_steps steps, one
-    // batched time loop per (operand dtype, engine) group
+    // batched time loop per (operand dtype, engine) group.  Grids whose plan fuses
+    // more than the batched launch's two steps (large 2-D grids) run their own
+    // fused launches instead, with the request's scratch buffer.
     std::vector<int> adv;
     std::map<int, std::vector<spider_impl::BatchItem>> groups;
+    std::vector<spider_impl::BatchItem> solo;
     for (ServerRequest* r : round) {
       const int k = std::min(r->remaining, S->round_steps);
-      const int key = r->plan->operand * 8 + r->plan->engine;
-      groups[key].push_back({r->plan, r->started ? r->out : r->in, r->out, r->scratch, k});
+      const spider_impl::BatchItem it{r->plan, r->started ? r->out : r->in, r->out, r->scratch, k};
+      if (r->plan->time_block > 2 && r->plan->ndim == 2)
+        solo.push_back(it);
+      else
+        groups[r->plan->operand * 8 + r->plan->engine].push_back(it);
       adv.push_back(k);
     }
     spider_status st = SPIDER_OK;
@@ -406,6 +412,9 @@ void server_loop(spider_server_s* S) {
       st = spider_impl::enqueue_batch(S->arena, kv.second, S->stream);
       if (st != SPIDER_OK) break;
     }
+    for (size_t i = 0; st == SPIDER_OK && i < solo.size(); ++i)
+      st = spider_impl::enqueue_steps_scratch(solo[i].plan, solo[i].in, solo[i].out, solo[i].scratch, solo[i].steps,
+                                              S->stream);
     if (st == SPIDER_OK && hipStreamSynchronize(S->stream) != hipSuccess) st = SPIDER_ERR_HIP;
     std::lock_guard<std::mutex> lk(S->mu);
     std::vector<ServerRequest*> still;

@@ -332,11 +332,11 @@ static LoopShape loop_launches(const spider_plan_s* p, int steps) {
 }
 
 // Launches k in [k0, k1] of the loop `L`, reading `src` first.  Buffers b_k = out if
-// (L.total - k) is even, else scratch.
-static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* out, int k0, int k1,
+// (L.total - k) is even, else `scratch` (the plan's own, or a server request's).
+static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* out, void* scratch, int k0, int k1,
                                       const LoopShape& L, hipStream_t s) {
   for (int k = k0; k <= k1; ++k) {
-    void* dst = ((L.total - k) % 2 == 0) ? out : p->d_scratch;
+    void* dst = ((L.total - k) % 2 == 0) ? out : scratch;
     if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: launch %d reads and writes one buffer", k);
     const int kind = L.kind(k);
     spider_status st = kind == 3   ? launch_step2(p, src, dst, s)
@@ -350,18 +350,23 @@ static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* o
 
 // The buffer launch 1 reads: `in`, or the scratch copy of it when in == out and
 // launch 1 would write out (copied here).
-static spider_status first_source(spider_plan_s* p, const void* in, void* out, int total, hipStream_t s,
-                                  const void** src) {
+static spider_status first_source(spider_plan_s* p, const void* in, void* out, void* scratch, int total,
+                                  hipStream_t s, const void** src) {
   *src = in;
   if (in == out && (total - 1) % 2 == 0) {
-    hipError_t e = hipMemcpyAsync(p->d_scratch, in, p->grid_bytes, hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMemcpyAsync(scratch, in, p->grid_bytes, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    *src = p->d_scratch;
+    *src = scratch;
   }
   return SPIDER_OK;
 }
 
 spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int steps, hipStream_t s) {
+  return enqueue_steps_scratch(p, in, out, p->d_scratch, steps, s);
+}
+
+spider_status enqueue_steps_scratch(spider_plan_s* p, const void* in, void* out, void* scratch, int steps,
+                                    hipStream_t s) {
   if (steps == 0) {
     if (in != out) {
       hipError_t e = hipMemcpyAsync(out, in, p->grid_bytes, hipMemcpyDeviceToDevice, s);
@@ -371,9 +376,9 @@ spider_status enqueue_steps(spider_plan_s* p, const void* in, void* out, int ste
   }
   const LoopShape L = loop_launches(p, steps);
   const void* src;
-  spider_status st = first_source(p, in, out, L.total, s, &src);
+  spider_status st = first_source(p, in, out, scratch, L.total, s, &src);
   if (st != SPIDER_OK) return st;
-  return enqueue_launches(p, src, out, 1, L.total, L, s);
+  return enqueue_launches(p, src, out, scratch, 1, L.total, L, s);
 }
 
 // Capture the launches enqueued by `body` on the plan's capture stream as one
@@ -409,8 +414,8 @@ static spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, c
   static_assert(kGraphBody % 2 == 0, "a body must return to its first source");
   const int total = L.total;
   const void* src;
-  spider_status st = first_source(p, in, out, total, s, &src);
-  if (st == SPIDER_OK) st = enqueue_launches(p, src, out, 1, 1, L, s);
+  spider_status st = first_source(p, in, out, p->d_scratch, total, s, &src);
+  if (st == SPIDER_OK) st = enqueue_launches(p, src, out, p->d_scratch, 1, 1, L, s);
   int k = 2;
   while (st == SPIDER_OK && k <= total) {
     const int kind = L.kind(k);
@@ -424,7 +429,7 @@ static spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, c
         hipGraphExec_t exec = nullptr;
         // launches k .. k + kGraphBody - 1 of this loop: the same for every body
         st = capture(p, [&](hipStream_t cs) {
-          return enqueue_launches(p, from, out, k, k + kGraphBody - 1, L, cs);
+          return enqueue_launches(p, from, out, p->d_scratch, k, k + kGraphBody - 1, L, cs);
         }, &exec);
         if (st != SPIDER_OK) return st;
         if (p->body_graphs.size() >= 16) {  // bound the cache (rare: waits for queued work first)
@@ -440,7 +445,7 @@ static spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, c
     }
     if (st == SPIDER_OK && k <= run_end) {
       const void* from = ((total - (k - 1)) % 2 == 0) ? out : p->d_scratch;
-      st = enqueue_launches(p, from, out, k, run_end, L, s);
+      st = enqueue_launches(p, from, out, p->d_scratch, k, run_end, L, s);
       k = run_end + 1;
     }
   }

@@ -218,3 +218,41 @@ def test_server_zero_steps_in_place_and_threads():
             assert np.array_equal(from_dev(o), want), (k, st, ip)
     finally:
         srv.close()
+
+
+def test_server_runs_deeply_fused_grids_on_their_own(oracle_mod):
+    # a 2-D grid large enough that its plan fuses three steps runs its own fused
+    # launches inside the server's rounds (small grids stay batched); integer data
+    # keeps every result exact over several rounds
+    import torch
+    shape = (2048, 4096)                       # 2^23 points: three fused steps
+    shift = np.zeros((7, 7))
+    shift[2, 5] = 1.0                          # one tap: values move, never grow
+    taps = np.zeros((7, 7))
+    taps[3, 3], taps[0, 6], taps[5, 1] = 1.0, -1.0, 1.0
+    x = si.grid_integer(shape, -2, 2, 91)
+    xd, x64 = to_dev(x, "f16")
+    small = si.workload("box2d49p_10240", small=True)
+    xs, _ = to_dev(small["make_grid"](), "f16")
+    srv = sp.Server(hbm_budget_bytes=1 << 30, max_slots=8)
+    try:
+        jobs = [(shift, 21, False), (shift, 19, True), (taps, 6, False)]
+        plans, outs, tickets = [], [], []
+        for w, st, in_place in jobs:
+            p = sp.Plan(w, shape, carry="f16")
+            assert p.info()["time_block"] == 3
+            src = xd.clone() if in_place else xd
+            o = src if in_place else torch.empty_like(xd)
+            tickets.append(srv.submit(p, src, o, st))
+            plans.append(p)
+            outs.append(o)
+        ps = sp.Plan(small["coeffs"], small["shape"], carry="f16")
+        os_ = torch.empty_like(xs)
+        tickets.append(srv.submit(ps, xs, os_, 20))
+        res = _wait(srv, tickets)
+        assert all(v == 0 for v in res.values())
+        for (w, st, in_place), o in zip(jobs, outs):
+            assert np.array_equal(from_dev(o), oracle_mod.apply(w, x64, st)), (st, in_place)
+        assert np.array_equal(from_dev(os_), _alone(small, xs, 20))
+    finally:
+        srv.close()
