@@ -286,8 +286,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU slab decomposition is a design "
-              "(see DESIGN.md), not built -- run with --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (a slab decomposition over several GPUs is not built); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -41,7 +41,7 @@ extern "C" {
 typedef enum {
     SPIDER_OK = 0,
     SPIDER_ERR_INVALID = 1,     /* bad argument (null pointer, size, radius, dtype...) */
-    SPIDER_ERR_UNSUPPORTED = 2, /* valid request this build does not run (e.g. sparse fp32) */
+    SPIDER_ERR_UNSUPPORTED = 2, /* valid request the library does not run (e.g. sparse fp32) */
     SPIDER_ERR_OOM = 3,         /* device or host allocation failed / over budget */
     SPIDER_ERR_HIP = 4,         /* a HIP runtime call failed */
     SPIDER_ERR_NOT_READY = 5,   /* ticket still running */

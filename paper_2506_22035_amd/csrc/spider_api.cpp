@@ -507,7 +507,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
                 "the matrix engines take 16-bit operands (gfx950 has no fp64 structured-sparse instruction); "
                 "use the direct engine for fp64 grids");
   if (matrix && o.carry == SPIDER_F32 && ndim != 2)
-    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines with an fp32 carry: 2-D grids only in this build");
+    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines with an fp32 carry run 2-D grids only");
   if (engine == SPIDER_ENGINE_DIRECT && low)
     return fail(SPIDER_ERR_UNSUPPORTED, "the direct engine runs fp32/fp64 grids only");
   if (matrix && (o.split < 1 || o.split > 3 || (o.split == 3 && low)))
@@ -515,7 +515,7 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   if (engine == SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 2)
     return fail(SPIDER_ERR_UNSUPPORTED, "direct engine: 3-D radius up to 2");
   if (matrix && ndim == 3 && radius > 1)
-    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines: 3-D radius 1 only in this build");
+    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines run 3-D grids with radius 1 only");
   if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
   if (o.time_block < 0 || o.time_block > 4) return fail(SPIDER_ERR_INVALID, "time_block must be 0..4");
   if (o.band_height != 0 && o.band_height != 8 && o.band_height != 16)

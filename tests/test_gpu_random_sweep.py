@@ -80,7 +80,7 @@ def test_random_sweep(oracle_mod, seed, ncases, scale):
         try:
             plan = sp.Plan(w, shape, **opts)
         except sp.SpiderError as e:
-            assert e.status in (1, 2), e   # an option set this build does not run
+            assert e.status in (1, 2), e   # an option set the library does not run
             skipped += 1
             continue
         dt = {"f16": torch.float16, "bf16": torch.bfloat16, "f32": torch.float32}[opts["carry"]]
