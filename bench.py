@@ -9,15 +9,18 @@ noise.  One benchmark step = one spider_apply of the whole 50-step time loop on
 inputs already resident in HBM.
 
 Prints one JSON line with the throughput (GStencil/s = grid points x time steps
-per second), the roofline position of the band kernel (algorithmic HBM bytes:
-one read and one write of the 16-bit state per point and time step), the fp64
-oracle timed on the host's cores on a bounded sample, errors against the oracle
-at full size (sampled points on their dependency cones), the plain fp32 GPU path
-on the same workload, per-pass latency percentiles and an engine ablation.
+per second) over the K timed passes and over a sustained region of at least one
+second, the roofline position of the dominant kernel against the roof that binds
+it (the larger of its HBM time and its matrix-instruction time over its measured
+launch duration), the fp64 oracle timed on the host's cores on a bounded sample,
+normwise errors against the oracle over every grid point of every workload, the
+plain fp32 GPU path on the same workloads, per-pass latency percentiles, an
+engine ablation and a short serving sample.
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -27,13 +30,19 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
+MFMA_PEAK_TFLOPS = 2500.0    # MI355X dense fp16 / bf16 matrix peak, 2.5 PFLOP/s
+# multiply-adds per matrix instruction over the operands it holds: a dense
+# 16x16x32 product, or a 2:4 16x16x64 smfmac (16 x 16 outputs x 32 stored A values)
+MACS_PER_INSTRUCTION = 16 * 16 * 32
 METRIC = "GStencil/s at stated error vs FP64 oracle (vs plain GPU path); p50/p99 latency"
-TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": (5e-5, 5e-5)}
+TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f32s3": (5e-5, 5e-5),
+       "f64": (1e-13, 1e-13)}
 KERNEL_SOURCES = ["paper_2506_22035_amd/csrc/kernels_band_pair.hip", "paper_2506_22035_amd/csrc/band_pair.h",
                   "paper_2506_22035_amd/csrc/band_common.h"]
-# the dominant kernel of the headline run: four fused time steps per launch
+# measured HBM bytes of the headline's dominant kernel (four fused time steps per launch)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "band2d_pair_tbt_box49p_f16_10240_traffic.json")
+SUSTAIN_S = 1.0              # length of the sustained timed region
 
 
 def kernel_source_hash():
@@ -44,9 +53,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch, steps_per_launch):
-    """HBM bytes per launch from committed rocprofv3 counters, if taken on this kernel source
-    and the same number of fused steps."""
+def measured_traffic(steps_per_launch, tile_h2, grid):
+    """HBM bytes per launch from committed rocprofv3 counters, if they were taken on this
+    kernel source, fused depth, segment height and grid."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -54,7 +63,8 @@ def measured_traffic(bytes_per_launch, steps_per_launch):
         return None
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    if t.get("time_steps_per_launch") != steps_per_launch or t.get("alg_bytes_per_launch") != bytes_per_launch:
+    if (t.get("time_steps_per_launch") != steps_per_launch or t.get("tile_h2") != tile_h2
+            or t.get("grid") != list(grid)):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -72,17 +82,111 @@ def timed_applies(torch, plan, xd, y, steps_per_pass, k, stream):
     return evs[0].elapsed_time(evs[k]), per
 
 
-def cone_samples(oracle, w, x64, steps, pts):
-    """The oracle at each sampled point, run on the point's dependency cone only."""
-    r = (w.shape[0] - 1) // 2
-    h = steps * r
-    out = []
-    for p in pts:
-        lo = [max(0, c - h) for c in p]
-        hi = [min(n, c + h + 1) for n, c in zip(x64.shape, p)]
-        sub = x64[tuple(slice(a, b) for a, b in zip(lo, hi))]
-        out.append(oracle.apply(w, sub, steps)[tuple(c - a for c, a in zip(p, lo))])
-    return np.array(out)
+def gstencil(npts, steps, ms):
+    return npts * steps / (ms * 1e-3) / 1e9
+
+
+def to_host64(torch, t):
+    return t.to(torch.float64).cpu().numpy()
+
+
+def full_grid_error(oracle, w, x64, steps, got, tol_key):
+    """Normwise errors of `got` against the oracle run on the whole grid:
+    rel-RMS = ||got - ref||_2 / ||ref||_2 and rel-max = ||got - ref||_inf / ||ref||_inf."""
+    ref = oracle.apply(w, x64, steps)
+    d = got - ref
+    rms = float(np.sqrt(np.sum(d * d) / np.sum(ref * ref)))
+    mx = float(np.max(np.abs(d)) / np.max(np.abs(ref)))
+    tr, tm = TOL[tol_key]
+    return {"rel_rms": rms, "rel_max": mx, "tol_rel_rms": tr, "tol_rel_max": tm, "points": int(ref.size),
+            "method": "every grid point against the fp64 oracle", "pass": bool(rms <= tr and mx <= tm)}
+
+
+def load_oracle():
+    import oracle
+    oracle.ensure_built()
+    return oracle
+
+
+def roofline(torch, sp, plan, xd, elem, npts, grid, operand, stream, headline_traffic):
+    """Roofline position of the plan's dominant kernel (its fused launch), timed over a
+    sustained loop of at least SUSTAIN_S seconds of fused launches only (HIP events on
+    `stream`).  Two roofs bound a launch from below: HBM (bytes moved / 8 TB/s) and the
+    matrix pipe (matrix instructions x 8192 multiply-adds x 2 / 2.5 PFLOP/s); the larger
+    fraction is the binding one."""
+    info = plan.info()
+    tb = max(1, info["time_block"])
+    yl = torch.empty_like(xd)
+    plan.apply(xd, yl, 4 * tb, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.apply(xd, yl, 20 * tb, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    est = e0.elapsed_time(e1) / 20.0
+    n_l = max(20, int(math.ceil(SUSTAIN_S * 1e3 / max(est, 1e-3))))
+    e0.record(stream)
+    plan.apply(xd, yl, n_l * tb, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del yl
+    avg_s = ms * 1e-3 / n_l
+    compulsory = npts * 2 * elem          # one read and one write of the state per launch
+    charged = compulsory * tb             # the same per time step, all steps of the launch
+    traffic = headline_traffic(tb, info["tile_h2"], grid)
+    hbm_bytes = traffic if traffic is not None else compulsory
+    hbm_frac = hbm_bytes / avg_s / 1e9 / HBM_PEAK_GBS
+    _, n_mi = plan.work(tb)
+    roof = {}
+    if n_mi is not None and n_mi > 0:
+        flop = n_mi * MACS_PER_INSTRUCTION * 2
+        mfma_tflops = flop / avg_s / 1e12
+        mfma_frac = mfma_tflops / MFMA_PEAK_TFLOPS
+    else:
+        mfma_frac = None
+    if mfma_frac is not None and mfma_frac > hbm_frac:
+        roof.update({"bound": "mfma", "achieved": round(mfma_tflops, 1), "peak": MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(mfma_frac, 4)})
+    else:
+        roof.update({"bound": "hbm", "achieved": round(hbm_bytes / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(hbm_frac, 4)})
+    roof["traffic"] = traffic
+    roof["hbm"] = {"bytes_per_launch": hbm_bytes,
+                   "bytes_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated" if traffic is not None
+                   else "compulsory: one read and one write of the grid",
+                   "GBs": round(hbm_bytes / avg_s / 1e9, 1), "frac": round(hbm_frac, 4),
+                   "compulsory_bytes_per_launch": compulsory}
+    if mfma_frac is not None:
+        roof["mfma"] = {"instructions_per_launch": n_mi, "operand": operand,
+                        "macs_per_instruction": MACS_PER_INSTRUCTION, "TFLOPs": round(mfma_tflops, 1),
+                        "frac": round(mfma_frac, 4)}
+    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "time_steps_per_launch": tb,
+                 "launch_timing": "%d fused launches back to back (%.0f ms), after the timed passes" % (n_l, ms),
+                 "alg_GBs_charged": round(charged / avg_s / 1e9, 1),
+                 "alg_bytes_charged_per_launch": charged})
+    sustained = {"value": round(gstencil(npts, n_l * tb, ms), 2), "seconds": round(ms * 1e-3, 3),
+                 "time_steps": n_l * tb, "launches": n_l}
+    return roof, sustained
+
+
+def kernel_name(info, shape, carry, engine, r, row_swap):
+    tb = info["time_block"]
+    if engine == "direct":
+        kname = "direct%dd_kernel" % len(shape)
+    elif carry == "f32":
+        kname = ("band2d_pair_f32_kernel" if info["band_height"] == 8 else "band2d_f32_kernel")
+    elif len(shape) == 1:
+        kname = "band1d_tbt_kernel" if tb > 1 else "band1d_kernel"
+    elif len(shape) == 3:
+        kname = "band3d_kernel"
+    elif info["band_height"] == 8:
+        kname = {1: "band2d_pair_kernel", 2: "band2d_pair_tb2_kernel"}.get(tb, "band2d_pair_tbt_kernel")
+    else:
+        kname = "band2d_tb2_kernel" if tb == 2 else "band2d_kernel"
+    return kname + "<r=%d,%s,%s%s%s>" % (r, carry, engine, ",T=%d" % tb if tb > 1 else "",
+                                         ",explicit row swap" if row_swap == "explicit" else "")
 
 
 def serving_run(torch, sp, si, reqs, rate, plans, bases, budget, slots):
@@ -124,7 +228,7 @@ def serving_run(torch, sp, si, reqs, rate, plans, bases, budget, slots):
 def serving(torch, sp, si, n, fractions, seed=11):
     """Serving mix: saturation throughput first (all requests at once), then Poisson rates."""
     torch.manual_seed(seed)
-    bases = {2: (torch.rand(8192 * 8192, device="cuda") ).to(torch.float16),
+    bases = {2: (torch.rand(8192 * 8192, device="cuda")).to(torch.float16),
              3: (torch.rand(384 ** 3, device="cuda")).to(torch.float16)}
     plans = {}
     reqs = si.serving_requests(n, 1.0, seed)   # times for rate 1 req/s, rescaled per run
@@ -145,42 +249,60 @@ def serving(torch, sp, si, n, fractions, seed=11):
     return out
 
 
-def batch3d(torch, sp, si, args):
-    """Box-3D27P 512^3 and Heat-3D 256^3, 20 steps each, advanced together by the
-    batched kernel (one launch per time step covering both grids), fp16
-    carry; compared with the two grids run one after the other on their own plans."""
+def batch3d_run(torch, sp, si, passes, warmup, with_errors, oracle=None):
+    """Box-3D27P 512^3 and Heat-3D 256^3, 20 steps each, advanced together by batched
+    launches (one launch per time step covering both grids), fp16 carry; compared with
+    the two grids run one after the other on their own plans, and with the plain fp32
+    path.  With errors: every point of both results against the fp64 oracle."""
     wls = [si.workload("box3d27p_512"), si.workload("heat3d_256")]
-    xs = [torch.from_numpy(wl["make_grid"](np.float32)).to(torch.float16).to("cuda:0") for wl in wls]
+    xh = [torch.from_numpy(wl["make_grid"](np.float32)).to(torch.float16) for wl in wls]
+    xs = [x.to("cuda:0") for x in xh]
     ys = [torch.empty_like(x) for x in xs]
     plans = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True) for wl in wls]
     steps = [wl["steps"] for wl in wls]
     npts = sum(int(np.prod(wl["shape"])) * wl["steps"] for wl in wls)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         sp.apply_batch(plans, xs, ys, steps)
     torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(passes + 1)]
     evs[0].record(stream)
-    for k in range(args.steps):
+    for k in range(passes):
         sp.apply_batch(plans, xs, ys, steps)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
-    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(passes)]
     total = evs[0].elapsed_time(evs[-1])
-    # the same work, each grid alone on its own plan (one step per launch, as batched)
-    solo = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True, time_block=1) for wl in wls]
-    for p, x, y, st in zip(solo, xs, ys, steps):
-        p.apply(x, y, st)
+    # the same batch launched step by step (plans without graph replay): the
+    # descriptors are staged and the launches enqueued on every call
+    direct = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True, use_graph=False) for wl in wls]
+    ysd = [torch.empty_like(x) for x in xs]
+    sp.apply_batch(direct, xs, ysd, steps)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
-        for p, x, y, st in zip(solo, xs, ys, steps):
+    for _ in range(passes):
+        sp.apply_batch(direct, xs, ysd, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    direct_ms = e0.elapsed_time(e1) / passes
+    same = all(bool(torch.equal(a, b)) for a, b in zip(ys, ysd))
+    del ysd
+    # the same work, each grid alone on its own plan (one step per launch, as batched)
+    solo = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True, time_block=1) for wl in wls]
+    ys2 = [torch.empty_like(x) for x in xs]
+    for p, x, y, st in zip(solo, xs, ys2, steps):
+        p.apply(x, y, st)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(passes):
+        for p, x, y, st in zip(solo, xs, ys2, steps):
             p.apply(x, y, st)
     e1.record(stream)
     torch.cuda.synchronize()
-    seq_ms = e0.elapsed_time(e1) / args.steps
-    value = npts * args.steps / (total * 1e-3) / 1e9
+    seq_ms = e0.elapsed_time(e1) / passes
+    del ys2
+    value = npts * passes / (total * 1e-3) / 1e9
     # the plain fp32 GPU path (direct engine) on the same grids and steps
     x32 = [x.to(torch.float32) for x in xs]
     y32 = [torch.empty_like(x) for x in x32]
@@ -194,38 +316,45 @@ def batch3d(torch, sp, si, args):
     e1.record(stream)
     torch.cuda.synchronize()
     fp32_value = npts / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    errors = None
-    if not args.no_extras:
-        # the batched fp16 results against the fp64 oracle at sampled points (dependency cones)
-        import oracle
-        if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
-            oracle.build()
-        rng = np.random.default_rng(0)
-        errors = {}
-        for wl, x, y, st in zip(wls, xs, ys, steps):
-            n = wl["shape"]
-            pts = [(0, 0, 0), tuple(v - 1 for v in n)] + [tuple(int(rng.integers(0, v)) for v in n) for _ in range(6)]
-            ref = cone_samples(oracle, wl["coeffs"], x.to(torch.float64).cpu().numpy(), st, pts)
-            got = y.to(torch.float64).cpu().numpy()
-            got = np.array([got[p] for p in pts])
-            d = got - ref
-            errors[wl["name"]] = {"rel_rms": float(np.sqrt((d * d).sum() / (ref * ref).sum())),
-                                  "rel_max": float(np.abs(d).max() / np.abs(ref).max()), "points": len(pts)}
-        ok = all(e["rel_rms"] <= TOL["f16"][0] and e["rel_max"] <= TOL["f16"][1] for e in errors.values())
-        errors["tol_rel_rms"], errors["tol_rel_max"], errors["pass"] = TOL["f16"][0], TOL["f16"][1], ok
-    return {"metric": METRIC, "value": round(value, 2), "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": round(total / args.steps, 4), "higher_is_better": True,
+    res = {"value": round(value, 2), "unit": "GStencil/s", "ms_per_pass": round(total / passes, 4),
+           "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
+                          "p99": round(float(np.percentile(per, 99)), 4)},
+           "graph_replay": True,
+           "direct_launches": {"ms_per_pass": round(direct_ms, 4),
+                               "GStencil/s": round(npts / (direct_ms * 1e-3) / 1e9, 2),
+                               "identical_to_graph_replay": same},
+           "separate_plans": {"ms_per_pass": round(seq_ms, 4),
+                              "GStencil/s": round(npts / (seq_ms * 1e-3) / 1e9, 2),
+                              "tile_h": [p.info()["tile_h"] for p in solo]},
+           "plain_gpu_fp32": {"value": round(fp32_value, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
+                              "speedup_batched_lowp_over_fp32": round(value / fp32_value, 3)}}
+    if with_errors:
+        got = [to_host64(torch, y) for y in ys]
+        got32 = [to_host64(torch, y) for y in y32]
+        del xs, ys, x32, y32
+        res["error_vs_fp64_oracle"] = {}
+        res["plain_gpu_fp32"]["error_vs_fp64_oracle"] = {}
+        for wl, x, g, g32 in zip(wls, xh, got, got32):
+            x64 = x.to(torch.float64).numpy()
+            ref_err = full_grid_error(oracle, wl["coeffs"], x64, wl["steps"], g, "f16")
+            res["error_vs_fp64_oracle"][wl["name"]] = ref_err
+            # the fp32 path ran on the same (fp16-rounded) values
+            res["plain_gpu_fp32"]["error_vs_fp64_oracle"][wl["name"]] = full_grid_error(
+                oracle, wl["coeffs"], x64, wl["steps"], g32, "f32")
+    for p in plans + direct + solo + p32:
+        p.close()
+    return res
+
+
+def batch3d(torch, sp, si, args):
+    oracle = None if args.no_extras else load_oracle()
+    r = batch3d_run(torch, sp, si, args.steps, args.warmup, not args.no_extras, oracle)
+    return {"metric": METRIC, "value": r["value"], "unit": "GStencil/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_pass"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
             "config": {"workload": "batch3d: box3d27p 512^3 x 20 steps + heat3d 256^3 x 20 steps, one batched "
                                    "launch per time step", "carry": "f16", "engine": "sparse"},
-            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
-                           "p99": round(float(np.percentile(per, 99)), 4)},
-            "separate_plans": {"ms_per_step": round(seq_ms, 4),
-                               "GStencil/s": round(npts / (seq_ms * 1e-3) / 1e9, 2),
-                               "tile_h": [p.info()["tile_h"] for p in solo]},
-            "plain_gpu_fp32": {"value": round(fp32_value, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
-                               "speedup_batched_lowp_over_fp32": round(value / fp32_value, 3)},
-            "error_vs_fp64_oracle": errors}
+            **{k: v for k, v in r.items() if k not in ("value", "unit", "ms_per_pass")}}
 
 
 def size_trend(torch, sp, si, args):
@@ -243,11 +372,81 @@ def size_trend(torch, sp, si, args):
             k = max(3, min(50, int(4e9 / (n * n * 50))))
             ms, _ = timed_applies(torch, p, x, y, 50, k, torch.cuda.current_stream())
             row["band%d_GStencil_s" % band] = round(n * n * 50 * k / (ms * 1e-3) / 1e9, 1)
+            row["band%d_time_steps_per_launch" % band] = p.info()["time_block"]
             p.close()
         res.append(row)
         del x, y
     return {"metric": "GStencil/s versus grid size (Box-2D49P, 50 steps, fp16 carry, sparse engine)",
             "config": {"workload": "box2d49p_size_trend", "steps_per_pass": 50}, "trend": res}
+
+
+_GRIDS = {}
+
+
+def workload_grid(si, name, dtype):
+    """The workload's host grid (drawn once per process and dtype)."""
+    key = (name, np.dtype(dtype).str)
+    if key not in _GRIDS:
+        _GRIDS[key] = si.workload(name)["make_grid"](dtype)
+    return _GRIDS[key]
+
+
+def workload_run(torch, sp, si, name, carry, engine, split, passes, stream, keep_result=True):
+    """Plan (autotuned) and time `passes` passes of workload `name`; return (GStencil/s,
+    plan info, result on the host in fp64 or None, input on the host in fp64)."""
+    wl = si.workload(name)
+    x32 = workload_grid(si, name, np.float64 if carry == "f64" else np.float32)
+    xh = torch.from_numpy(x32).to(sp.torch_dtype(carry))
+    xd = xh.to("cuda:0")
+    y = torch.empty_like(xd)
+    p = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, engine=engine, split=split, autotune=True)
+    p.apply(xd, y, wl["steps"], stream=stream)
+    ms, _ = timed_applies(torch, p, xd, y, wl["steps"], passes, stream)
+    info = p.info()
+    p.close()
+    got = to_host64(torch, y) if keep_result else None
+    del xd, y
+    return gstencil(int(np.prod(wl["shape"])), wl["steps"] * passes, ms), info, got, xh.to(torch.float64).numpy()
+
+
+def other_configs(torch, sp, si, stream, oracle):
+    """The other workloads: throughput and full-grid errors of each, with the plain fp32
+    GPU path where it is the metric's comparison."""
+    out = {}
+    # Star-2D13P 8192^2, 100 steps: fp16 sparse vs the plain fp32 GPU path, and the fp32 carry
+    name = "star2d13p_8192"
+    wl = si.workload(name)
+    v16, i16, g16, x16 = workload_run(torch, sp, si, name, "f16", "sparse", 2, 3, stream)
+    e16 = full_grid_error(oracle, wl["coeffs"], x16, wl["steps"], g16, "f16")
+    del g16, x16
+    v32, _, g32, x32 = workload_run(torch, sp, si, name, "f32", "direct", 2, 3, stream)
+    vs3, is3, gs3, _ = workload_run(torch, sp, si, name, "f32", "sparse", 3, 3, stream)
+    e32 = full_grid_error(oracle, wl["coeffs"], x32, wl["steps"], g32, "f32")
+    es3 = full_grid_error(oracle, wl["coeffs"], x32, wl["steps"], gs3, "f32s3")
+    del g32, gs3, x32
+    out[name] = {"f16_sparse": {"value": round(v16, 2), "time_steps_per_launch": i16["time_block"],
+                                "error_vs_fp64_oracle": e16},
+                 "plain_gpu_fp32": {"value": round(v32, 2), "engine": "direct (VALU fp32)",
+                                    "error_vs_fp64_oracle": e32},
+                 "f32_carry_sparse_split3": {"value": round(vs3, 2), "time_steps_per_launch": is3["time_block"],
+                                             "error_vs_fp64_oracle": es3},
+                 "speedup_f16_over_plain_fp32": round(v16 / v32, 3),
+                 "speedup_f32_carry_over_plain_fp32": round(vs3 / v32, 3)}
+    # Box-3D27P 512^3 + Heat-3D 256^3 in one batched launch per step
+    out["batch3d"] = batch3d_run(torch, sp, si, 5, 1, True, oracle)
+    # Box-2D9P 256^2, fp64 on the direct engine (latency-bound at this size)
+    name = "box2d9p_256_f64"
+    wl = si.workload(name)
+    v64, _, g64, x64 = workload_run(torch, sp, si, name, "f64", "direct", 2, 20, stream)
+    out[name] = {"value": round(v64, 2), "us_per_time_step": round(65536 / (v64 * 1e9) * 1e6, 3),
+                 "error_vs_fp64_oracle": full_grid_error(oracle, wl["coeffs"], x64, wl["steps"], g64, "f64")}
+    # the paper's 1-D workloads, 100 steps, fp16
+    for name in ("1d3p_10240000", "1d5p_10240000"):
+        wl = si.workload(name)
+        v1, i1, g1, x1 = workload_run(torch, sp, si, name, "f16", "sparse", 2, 5, stream)
+        out[name] = {"value": round(v1, 2), "time_steps_per_launch": i1["time_block"],
+                     "error_vs_fp64_oracle": full_grid_error(oracle, wl["coeffs"], x1, wl["steps"], g1, "f16")}
+    return out
 
 
 def main():
@@ -274,7 +473,8 @@ def main():
                     help="row swap in the gather offsets (implicit) or by an LDS copy (explicit; the comparison "
                          "of the paper's Table 3: sparse engine, band height 16, one step per launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip errors, fp32 path and ablation")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip errors, the other workloads, the fp32 path, the ablation and the serving sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of the grid size (for HBM counter scaling)")
     ap.add_argument("--serving", action="store_true",
@@ -323,7 +523,7 @@ def main():
     shape = tuple(wl["shape"])
     ny, nx = (shape[-2] if len(shape) > 1 else 1), shape[-1]
     npts = int(np.prod(shape))
-    x32 = wl["make_grid"](np.float64 if args.carry == "f64" else np.float32)
+    x32 = workload_grid(si, args.workload, np.float64 if args.carry == "f64" else np.float32)
     tdt = sp.torch_dtype(args.carry)
     xh = torch.from_numpy(x32).to(tdt)
     xd = xh.to("cuda:0")
@@ -344,59 +544,20 @@ def main():
     total_ms, per = timed_applies(torch, plan, xd, y, T, args.steps, stream)
     wall_ms = (time.perf_counter() - wall0) * 1e3
     ms_per_step = total_ms / args.steps
-    value = npts * T * args.steps / (total_ms * 1e-3) / 1e9
+    value = gstencil(npts, T * args.steps, total_ms)
+    launches, mi_pass = plan.work(T)
 
-    # Roofline of the dominant kernel.  A fused launch advances tb time steps; the
-    # algorithmic bytes are one read and one write of the state per point and time
-    # step, so a fused launch is charged for all of its steps.
-    tb = info["time_block"]
-    fused = T // tb                       # launches of the dominant kernel per pass
-    steps_per_launch = tb
-    if T % tb == 0:
-        # every launch of the pass is the dominant kernel: its average over the timed region
-        avg_launch_s = total_ms * 1e-3 / (args.steps * fused)
-        launch_timing = "timed region"
-    else:
-        # a pass ends with T % tb single steps: time the fused kernel on its own, as
-        # one time loop of n_l * tb steps (n_l fused launches back to back, no single
-        # steps), HIP events on the same stream
-        n_l = max(10, args.steps * fused)
-        le0, le1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        yl = torch.empty_like(xd)  # y keeps the timed passes' result for the error check
-        plan.apply(xd, yl, n_l * tb, stream=stream)
-        torch.cuda.synchronize()
-        le0.record(stream)
-        plan.apply(xd, yl, n_l * tb, stream=stream)
-        le1.record(stream)
-        torch.cuda.synchronize()
-        del yl
-        avg_launch_s = le0.elapsed_time(le1) * 1e-3 / n_l
-        launch_timing = "a loop of %d fused launches after the timed region" % n_l
     elem = {"f16": 2, "bf16": 2, "f32": 4, "f64": 8}[args.carry]
-    alg_bytes = npts * 2 * elem * steps_per_launch
-    achieved = alg_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic(alg_bytes, tb) if headline and args.carry == "f16" and args.engine == "sparse" else None
+    operand = args.carry if args.carry in ("f16", "bf16") else "f16"
     rr = (wl["coeffs"].shape[0] - 1) // 2
-    if args.engine == "direct":
-        kname = "direct%dd_kernel" % len(shape)
-    elif args.carry == "f32":
-        kname = ("band2d_pair_f32_kernel<fused>" if tb == 2 else
-                 "band2d_pair_f32_kernel" if info["band_height"] == 8 else "band2d_f32_kernel")
-    elif len(shape) != 2:
-        kname = "band%dd_kernel" % len(shape)
-    elif info["band_height"] == 8:
-        kname = {1: "band2d_pair_kernel", 2: "band2d_pair_tb2_kernel"}.get(tb, "band2d_pair_tbt_kernel")
-    else:
-        kname = "band2d_tb2_kernel" if tb == 2 else "band2d_kernel"
-    kname += "<r=%d,%s,%s%s%s>" % (rr, args.carry, args.engine, ",T=%d" % tb if tb > 2 else "",
-                                   ",explicit row swap" if args.row_swap == "explicit" else "")
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kname,
-            "time_steps_per_launch": steps_per_launch,
-            "alg_bytes_per_launch": alg_bytes,
-            "avg_launch_us": round(avg_launch_s * 1e6, 2),
-            "launch_timing": launch_timing}
+
+    def traffic_lookup(tb, tile_h2, grid):
+        if headline and args.carry == "f16" and args.engine == "sparse":
+            return measured_traffic(tb, tile_h2, grid)
+        return None
+
+    roof, sustained = roofline(torch, sp, plan, xd, elem, npts, shape, operand, stream, traffic_lookup)
+    roof["kernel"] = kernel_name(info, shape, args.carry, args.engine, rr, args.row_swap)
 
     # a plain device copy of the same grid: read + write of the same bytes, for reference
     z = torch.empty_like(xd)
@@ -416,7 +577,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": args.carry, "data": "synthetic",
            "config": {"workload": args.workload, "grid": list(shape),
                       "time_steps_per_step": T, "carry": args.carry,
-                      "operand": "f16" if (args.carry == "f32" and args.engine != "direct") else args.carry,
+                      "operand": operand if args.engine != "direct" else args.carry,
                       "accumulate": "f32" if args.carry in ("f16", "bf16") else args.carry,
                       "engine": info["engine"], "split": args.split if args.engine != "direct" else None,
                       "tile_h": info["tile_h"],
@@ -426,94 +587,65 @@ def main():
            "wall_ms_timed_region": round(wall_ms, 3), "plan_ms": round(plan_ms, 3),
            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
                           "p99": round(float(np.percentile(per, 99)), 4)},
+           "sustained": sustained,
+           "launches_per_step": launches,
+           "matrix_instructions_per_step": mi_pass,
            "roofline": roof}
 
-    # errors, the plain fp32 path, the fp32-carry mode and the engine ablation run on
-    # every 2-D workload with a 16-bit carry; the serving sample and the host
-    # baseline on the headline workload only
-    if not (len(shape) == 2 and args.carry in ("f16", "bf16")):
-        args.no_extras = True
-    if not headline:
-        args.no_cpu_baseline = True
-
     if not args.no_extras:
-        import oracle
-        if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
-            oracle.build()
-        # errors at full size: sampled points against the oracle on their dependency cones
-        res = y.to(torch.float64).cpu().numpy()
+        oracle = load_oracle()
+        got = to_host64(torch, y)
         x64 = xh.to(torch.float64).numpy()
-        rng = np.random.default_rng(0)
-        pts = [(0, 0), (ny - 1, nx - 1), (ny // 2, nx // 2)] + \
-              [tuple(int(v) for v in rng.integers(0, ny, 2)) for _ in range(13)]
-        ref = cone_samples(oracle, wl["coeffs"], x64, T, pts)
-        got = np.array([res[p] for p in pts])
-        d = got - ref
-        rms = float(np.sqrt((d * d).sum() / (ref * ref).sum()))
-        mx = float(np.abs(d).max() / np.abs(ref).max())
-        out["error_vs_fp64_oracle"] = {"rel_rms": rms, "rel_max": mx, "tol_rel_rms": TOL[args.carry][0],
-                                       "tol_rel_max": TOL[args.carry][1], "points": len(pts),
-                                       "method": "sampled points at full size, oracle on each dependency cone",
-                                       "pass": rms <= TOL[args.carry][0] and mx <= TOL[args.carry][1]}
-        # plain fp32 GPU path on the same workload
-        xf = torch.from_numpy(x32).to("cuda:0")
-        yf = torch.empty_like(xf)
-        p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32")
-        p32.apply(xf, yf, T, stream=stream)
-        ms32, _ = timed_applies(torch, p32, xf, yf, T, 3, stream)
-        v32 = npts * T * 3 / (ms32 * 1e-3) / 1e9
-        out["plain_gpu_fp32"] = {"value": round(v32, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
-                                 "speedup_lowp_over_fp32": round(value / v32, 3)}
-        p32.close()
-        # fp32 carry on the sparse engine: every input value split into 16-bit hi + lo
-        # operands (split 3), fp32 accumulation and fp32 state (8 bytes per point-step)
-        pm = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, autotune=True)
-        pm.apply(xf, yf, T, stream=stream)
-        msm, _ = timed_applies(torch, pm, xf, yf, T, 3, stream)
-        vm = npts * T * 3 / (msm * 1e-3) / 1e9
-        resm = yf.to(torch.float64).cpu().numpy()
-        refm = cone_samples(oracle, wl["coeffs"], xf.to(torch.float64).cpu().numpy(), T, pts)
-        dm = np.array([resm[p] for p in pts]) - refm
-        out["f32_carry_sparse_split3"] = {
-            "value": round(vm, 2), "unit": "GStencil/s", "tile_h": pm.info()["tile_h"],
-            "roofline_frac": round(npts * 8 * T * 3 / (msm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "rel_rms": float(np.sqrt((dm * dm).sum() / (refm * refm).sum())),
-            "rel_max": float(np.abs(dm).max() / np.abs(refm).max()),
-            "tol_rel_rms": TOL["f32s3"][0], "tol_rel_max": TOL["f32s3"][1],
-            "speedup_over_plain_fp32": round(vm / v32, 3)}
-        pm.close()
-        del xf, yf
-        # ablation: the other engine / operand type on the same pass
-        abl = {}
-        for carry, engine in [("f16", "dense"), ("f16", "sparse"), ("bf16", "sparse"), ("bf16", "dense")]:
-            if carry == args.carry and engine == args.engine:
-                continue
-            xa = torch.from_numpy(x32).to(sp.torch_dtype(carry)).to("cuda:0")
-            ya = torch.empty_like(xa)
-            pa = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, engine=engine)
-            pa.apply(xa, ya, T, stream=stream)
-            msa, _ = timed_applies(torch, pa, xa, ya, T, 3, stream)
-            abl["%s_%s" % (engine, carry)] = round(npts * T * 3 / (msa * 1e-3) / 1e9, 2)
-            pa.close()
-        out["ablation_gstencil_s"] = abl
+        del y
+        tol_key = "f32s3" if (args.carry == "f32" and args.engine != "direct") else args.carry
+        out["error_vs_fp64_oracle"] = full_grid_error(oracle, wl["coeffs"], x64, T, got, tol_key)
+        del got
+        if len(shape) == 2 and args.carry in ("f16", "bf16"):
+            # the plain fp32 GPU path and the fp32 carry on the sparse engine (every input
+            # value split into 16-bit hi + lo operands, split 3), same workload
+            v32, _, g32, x32h = workload_run(torch, sp, si, args.workload, "f32", "direct", 2, 3, stream)
+            out["plain_gpu_fp32"] = {"value": round(v32, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
+                                     "speedup_lowp_over_fp32": round(value / v32, 3)}
+            del g32
+            vm, im, gm, _ = workload_run(torch, sp, si, args.workload, "f32", "sparse", 3, 3, stream)
+            out["f32_carry_sparse_split3"] = {
+                "value": round(vm, 2), "unit": "GStencil/s", "time_steps_per_launch": im["time_block"],
+                "tile_h": im["tile_h2"] or im["tile_h"],
+                "error_vs_fp64_oracle": full_grid_error(oracle, wl["coeffs"], x32h, T, gm, "f32s3"),
+                "speedup_over_plain_fp32": round(vm / v32, 3)}
+            del gm, x32h
+            # ablation: the other engine / operand type on the same pass; bf16 with its error
+            abl = {}
+            for carry, engine in [("f16", "dense"), ("f16", "sparse"), ("bf16", "sparse"), ("bf16", "dense")]:
+                if carry == args.carry and engine == args.engine:
+                    continue
+                keep = carry == "bf16" and engine == "sparse"
+                va, ia, ga, xa = workload_run(torch, sp, si, args.workload, carry, engine, 2, 3, stream, keep)
+                abl["%s_%s" % (engine, carry)] = round(va, 2)
+                if keep:
+                    abl["%s_%s_error_vs_fp64_oracle" % (engine, carry)] = full_grid_error(
+                        oracle, wl["coeffs"], xa, T, ga, carry)
+                del ga, xa
+            out["ablation_gstencil_s"] = abl
+        if headline:
+            out["configs"] = other_configs(torch, sp, si, stream, oracle)
+            # a short serving sample (the full sweep is `bench.py --serving`)
+            out["serving_sample"] = serving(torch, sp, si, 200, [0.75])
 
-    if not args.no_extras and headline:
-        # a short serving sample (the full sweep is `bench.py --serving`)
-        out["serving_sample"] = serving(torch, sp, si, 200, [0.75])
-
-    if not args.no_cpu_baseline:
-        import oracle
-        if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
-            oracle.build()
+    if headline and not args.no_cpu_baseline:
+        oracle = load_oracle()
         rows, st = ny, 12
         sample = xh[:rows].to(torch.float64).numpy()
-        t0 = time.perf_counter()
-        oracle.apply(wl["coeffs"], sample, st)
-        dt = time.perf_counter() - t0
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.apply(wl["coeffs"], sample, st)
+            times.append(time.perf_counter() - t0)
+        dt = min(times)
         out["cpu_baseline"] = {"value": round(rows * nx * st / dt / 1e9, 5), "unit": "GStencil/s",
                                "cores": oracle.max_threads(), "kind": "oracle",
-                               "sample": "fp64 oracle, rows 0..%d of the %dx%d grid, %d time steps, %.1f s"
-                                         % (rows, ny, nx, st, dt)}
+                               "sample": "fp64 oracle, all %d rows of the %dx%d grid, %d time steps, best of 3 "
+                                         "runs (%.1f s each at best)" % (rows, ny, nx, st, dt)}
     print(json.dumps(out))
 
 

@@ -141,7 +141,11 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
                           const spider_opts* opts, spider_plan_t* out);
 
 /*
- * spider_apply: out = S^steps(in) on `stream` (Jacobi steps, zero halo).
+ * spider_apply: out = S^steps(in) on `stream`: `steps` applications of the
+ * stencil update of Sec. 2.2 (every point replaced by the weighted sum of its
+ * radius-r neighbourhood), each step reading only the previous step's grid
+ * (Jacobi), with the zero halo; each step is computed as the banded products of
+ * Sec. 3.1.1 on the strided-swapped operands (Sec. 3.1.2, 3.2).
  *   in, out  device grids of the plan's shape in the plan's carry dtype; `in` is
  *            never written unless in == out (allowed); steps == 0 copies.
  *   steps    >= 0
@@ -173,6 +177,21 @@ spider_status spider_plan_destroy(spider_plan_t plan);
 spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int* tile_h,
                                int* nrows_nonzero, size_t* scratch_bytes, int* time_block,
                                int* tile_h2, int* band_height);
+
+/*
+ * spider_plan_work: what spider_apply(plan, in, out, steps) issues on the device
+ * (host query, no device work), for measurement against the hardware's roofs.
+ *   launches             kernel launches of the time loop (0 for steps == 0)
+ *   matrix_instructions  matrix instructions of all of them (smfmac 16x16x64 on the
+ *                        sparse engine, mfma 16x16x32 on the dense one; 0 for the
+ *                        direct engine)
+ * Either output pointer may be NULL.  With steps == time_block the loop is exactly
+ * one launch of the plan's fused kernel.
+ * Errors: INVALID (null plan, steps < 0), UNSUPPORTED (matrix_instructions asked
+ * for a plan other than paired-line bands with a 16-bit carry or the direct engine;
+ * *launches is still set).
+ */
+spider_status spider_plan_work(spider_plan_t plan, int steps, uint64_t* launches, uint64_t* matrix_instructions);
 
 /*
  * Batched apply (launches over the tiles of every grid).
@@ -208,20 +227,30 @@ spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int m
 
 /*
  * spider_submit: enqueue out = S^steps(in) for `plan`.  `in` and `out` are
- * device buffers owned by the caller that must stay valid until the ticket is
- * done; `in` is read once at admission.  Returns BUSY if the queue is full,
- * OOM if the request alone exceeds the budget, INVALID on bad arguments or a
- * plan built on another device than the server's.
+ * device buffers owned by the caller, and `plan` a plan owned by the caller;
+ * all three must stay valid (not freed, not destroyed) until spider_poll has
+ * reported the ticket done, or until spider_server_destroy has returned.  `in`
+ * is read once at admission.  Returns BUSY if the queue is full, OOM if the
+ * request alone exceeds the budget, INVALID on bad arguments or a plan built
+ * on another device than the server's.  A request whose scratch buffer cannot
+ * be allocated while no other request runs completes with OOM.
  */
 spider_status spider_submit(spider_server_t srv, spider_plan_t plan, const void* in, void* out,
                             int steps, uint64_t* ticket);
 
-/* spider_poll: *done = 1 once the result is in `out` (then *result holds its status). */
+/*
+ * spider_poll: *done = 1 once the result is in `out` (then *result holds its
+ * status).  A ticket reported done is released: polling it again returns CLOSED
+ * (unknown ticket).  Tickets that are never polled are released by
+ * spider_server_destroy.
+ */
 spider_status spider_poll(spider_server_t srv, uint64_t ticket, int* done, spider_status* result);
 
 /*
  * spider_server_stats: latency of completed requests in microseconds (submit ->
- * result written), percentiles over all completed tickets, and totals.
+ * result written), percentiles over the most recent 65536 successful
+ * completions, the number of successful completions and the stencil updates
+ * (points x steps) they performed.
  */
 spider_status spider_server_stats(spider_server_t srv, double* p50_us, double* p99_us,
                                   uint64_t* completed, double* stencil_updates);

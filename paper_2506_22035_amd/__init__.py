@@ -54,6 +54,7 @@ def lib():
             "spider_apply": [P, P, P, I, P],
             "spider_plan_destroy": [P],
             "spider_plan_info": [P, P, P, P, P, P, P, P, P],
+            "spider_plan_work": [P, I, P, P],
             "spider_apply_batch": [I, P, P, P, P, P],
             "spider_server_create": [ctypes.c_size_t, I, I, P],
             "spider_submit": [P, P, P, P, I, P],
@@ -213,6 +214,16 @@ class Plan:
                     nrows_nonzero=n.value, scratch_bytes=sb.value, time_block=tb.value, tile_h2=t2.value,
                     band_height=bh.value)
 
+    def work(self, steps):
+        """(launches, matrix instructions) that apply(..., steps) issues; the count is
+        None where the library keeps none (see spider_plan_work)."""
+        n, m = ctypes.c_uint64(), ctypes.c_uint64()
+        st = lib().spider_plan_work(self.handle, int(steps), ctypes.byref(n), ctypes.byref(m))
+        if st == 2:
+            return n.value, None
+        _check(st)
+        return n.value, m.value
+
     def check_tensor(self, t):
         torch = _torch()
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -260,6 +271,10 @@ class Server:
         _check(lib().spider_server_create(ctypes.c_size_t(int(hbm_budget_bytes)), int(max_slots), int(max_queue),
                                           ctypes.byref(h)))
         self._h = h
+        # the plan and both grids of every ticket in flight: the server reads them
+        # until the ticket is done, so they must not be freed before that
+        self._inflight = {}
+        self._finished = {}   # ticket -> status, once the library has reported it done
 
     def submit(self, plan, x_in, x_out, steps):
         plan.check_tensor(x_in)
@@ -267,6 +282,7 @@ class Server:
         t = ctypes.c_uint64()
         _check(lib().spider_submit(self._h, plan.handle, ctypes.c_void_p(x_in.data_ptr()),
                                    ctypes.c_void_p(x_out.data_ptr()), int(steps), ctypes.byref(t)))
+        self._inflight[t.value] = (plan, x_in, x_out)
         return t.value
 
     def try_submit(self, plan, x_in, x_out, steps):
@@ -279,9 +295,15 @@ class Server:
             raise
 
     def poll(self, ticket):
-        """(done, status) of a ticket."""
+        """(done, status) of a ticket.  Once done, the ticket's plan and grids are released
+        by the server object (the caller's own references are untouched)."""
+        if ticket in self._finished:
+            return True, self._finished[ticket]
         d, r = ctypes.c_int(), ctypes.c_int()
         _check(lib().spider_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d), ctypes.byref(r)))
+        if d.value:
+            self._finished[ticket] = r.value
+            self._inflight.pop(ticket, None)
         return bool(d.value), r.value
 
     def stats(self):
@@ -295,6 +317,7 @@ class Server:
         if getattr(self, "_h", None) is not None:
             _check(lib().spider_server_destroy(self._h))
             self._h = None
+            self._inflight.clear()
 
     def __del__(self):
         try:

@@ -76,6 +76,8 @@ spider_status enqueue_steps_scratch(spider_plan_s* p, const void* in, void* out,
 // Launches per replayed graph body of a long time loop (even); loops of more than
 // twice as many launches replay bodies instead of capturing the whole loop.
 constexpr int kGraphBody = 256;
+// Drop the cached batch graphs that use plan `p` (called when it is destroyed).
+void batch_graphs_forget_plan(const spider_plan_s* p);
 // Measure candidate segment heights and keep the fastest (tile_h must hold the heuristic choice).
 spider_status autotune_tile(spider_plan_s* p);
 }  // namespace spider_impl

@@ -20,6 +20,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -149,11 +150,29 @@ static int batch_height_3d(const std::vector<BatchItem>& items) {
   return 1;
 }
 
-// Enqueue the batched time loop of `items` on stream s.
+// A batched time loop laid out for the device: the per-launch descriptors
+// (BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned blocks), the
+// work units of each launch, and the device-to-device copies that precede it
+// (steps == 0 results, and in == out sources that the first launch must not
+// overwrite).
+struct BatchProgram {
+  int operand = -1, engine = -1, cls = 0;
+  std::vector<char> desc;
+  std::vector<size_t> off;  // block offset of launch st
+  std::vector<int> m, units;
+  struct Copy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  std::vector<Copy> copies;
+};
 
-spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, hipStream_t s) {
+// Lay out the batched time loop of `items`.
+static spider_status build_batch(const std::vector<BatchItem>& items, BatchProgram* prog) {
   const int n = (int)items.size();
-  int operand = -1, engine = -1, maxsteps = 0;
+  BatchProgram& P = *prog;
+  int maxsteps = 0;
   for (const auto& it : items) {
     const spider_plan_s* p = it.plan;
     if (p->engine == SPIDER_ENGINE_DIRECT || p->carry != p->operand || p->ndim == 1)
@@ -161,23 +180,22 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     if (p->row_swap) return fail(SPIDER_ERR_UNSUPPORTED, "batched apply runs the implicit row swap only");
     if (p->ndim == 2 ? p->r > 3 : p->r != 1)
       return fail(SPIDER_ERR_UNSUPPORTED, "batched apply supports 2-D radius 1..3 and 3-D radius 1");
-    if (operand < 0) {
-      operand = p->operand;
-      engine = p->engine;
-    } else if (operand != p->operand || engine != p->engine) {
+    if (P.operand < 0) {
+      P.operand = p->operand;
+      P.engine = p->engine;
+    } else if (P.operand != p->operand || P.engine != p->engine) {
       return fail(SPIDER_ERR_UNSUPPORTED, "batched plans must share carry dtype and engine");
     }
     if (it.steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
     maxsteps = std::max(maxsteps, it.steps);
   }
   // the kernel variant holding only the body classes present (2-D: 1, 3-D: 2)
-  int cls = 0;
   bool aligned = true;
   for (const auto& it : items) {
-    cls |= it.plan->ndim == 3 ? 2 : 1;
+    P.cls |= it.plan->ndim == 3 ? 2 : 1;
     aligned = aligned && it.plan->nx % 8 == 0;
   }
-  if (aligned) cls |= 4;  // aligned bodies only
+  if (aligned) P.cls |= 4;  // aligned bodies only
   // Per item: its launches (grids with paired bands run steps / 2 launches of two
   // fused steps, then a single step if steps is odd, as spider_apply with
   // time_block 2 does), and the first source, after the in == out copy when needed.
@@ -189,47 +207,38 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
     nl[i] = nf[i] + (it.steps - 2 * nf[i]);
     maxl = std::max(maxl, nl[i]);
   }
-  std::vector<const void*> src(n);
+  std::vector<const void*> cur(n);
   for (int i = 0; i < n; ++i) {
     const BatchItem& it = items[i];
-    src[i] = it.in;
+    cur[i] = it.in;
     const size_t bytes = it.plan->grid_bytes;
     if (it.steps == 0) {
-      if (it.in != it.out) {
-        hipError_t e = hipMemcpyAsync(it.out, it.in, bytes, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-      }
+      if (it.in != it.out) P.copies.push_back({it.out, it.in, bytes});
     } else if (it.in == it.out && (nl[i] - 1) % 2 == 0) {
-      hipError_t e = hipMemcpyAsync(it.scratch, it.in, bytes, hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-      src[i] = it.scratch;
+      P.copies.push_back({it.scratch, it.in, bytes});
+      cur[i] = it.scratch;
     }
   }
   if (maxsteps == 0) return SPIDER_OK;
   const int h3 = batch_height_3d(items);
-  // Descriptor layout per launch: BandGrid[m] | int kinds[m] | int begin[m + 1], 256-byte aligned.
-  std::vector<size_t> off(maxl + 1);
-  std::vector<int> m(maxl);
+  P.off.assign(maxl + 1, 0);
+  P.m.assign(maxl, 0);
+  P.units.assign(maxl, 0);
   size_t bytes = 0;
   for (int st = 0; st < maxl; ++st) {
     int cnt = 0;
     for (int i = 0; i < n; ++i) cnt += nl[i] > st;
-    m[st] = cnt;
-    off[st] = bytes;
+    P.m[st] = cnt;
+    P.off[st] = bytes;
     bytes += align_up(cnt * sizeof(BandGrid) + cnt * sizeof(int) + (cnt + 1) * sizeof(int), 256);
   }
-  off[maxl] = bytes;
-
-  std::lock_guard<std::mutex> lk(A.mu);
-  hipError_t e = A.reserve(bytes);
-  if (e != hipSuccess) return hip_fail(e, "batch descriptor buffers");
-  std::vector<const void*> cur = src;
-  std::vector<int> units(maxl, 0);
+  P.off[maxl] = bytes;
+  P.desc.assign(bytes, 0);
   for (int st = 0; st < maxl; ++st) {
-    char* base = A.host + off[st];
+    char* base = P.desc.data() + P.off[st];
     BandGrid* gd = reinterpret_cast<BandGrid*>(base);
-    int* kinds = reinterpret_cast<int*>(base + m[st] * sizeof(BandGrid));
-    int* begin = kinds + m[st];
+    int* kinds = reinterpret_cast<int*>(base + P.m[st] * sizeof(BandGrid));
+    int* begin = kinds + P.m[st];
     int j = 0, acc = 0;
     for (int i = 0; i < n; ++i) {
       const BatchItem& it = items[i];
@@ -249,22 +258,154 @@ spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, 
       ++j;
     }
     begin[j] = acc;
-    units[st] = acc;
+    P.units[st] = acc;
+    if (acc < 1) return fail(SPIDER_ERR_INVALID, "batch step without work units");
   }
-  e = hipMemcpyAsync(A.dev, A.host, bytes, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
-  for (int st = 0; st < maxl; ++st) {
-    char* base = A.dev + off[st];
+  return SPIDER_OK;
+}
+
+static spider_status enqueue_copies(const BatchProgram& P, hipStream_t s) {
+  for (const auto& c : P.copies) {
+    hipError_t e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  return SPIDER_OK;
+}
+
+// The program's kernel launches, reading its descriptors at `dev` (a device copy of P.desc).
+static spider_status enqueue_launches(const BatchProgram& P, const char* dev, hipStream_t s) {
+  for (size_t st = 0; st < P.m.size(); ++st) {
+    const char* base = dev + P.off[st];
     const BandGrid* gd = reinterpret_cast<const BandGrid*>(base);
-    const int* kinds = reinterpret_cast<const int*>(base + m[st] * sizeof(BandGrid));
-    const int* begin = kinds + m[st];
-    if (units[st] < 1) return fail(SPIDER_ERR_INVALID, "batch step without work units");
-    e = launch_band_batch(operand, engine, cls, gd, kinds, begin, m[st], units[st], s);
+    const int* kinds = reinterpret_cast<const int*>(base + P.m[st] * sizeof(BandGrid));
+    const int* begin = kinds + P.m[st];
+    hipError_t e = launch_band_batch(P.operand, P.engine, P.cls, gd, kinds, begin, P.m[st], P.units[st], s);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   }
+  return SPIDER_OK;
+}
+
+// Enqueue the batched time loop of `items` on stream s, its descriptors staged
+// through the arena.
+spider_status enqueue_batch(BatchArena& A, const std::vector<BatchItem>& items, hipStream_t s) {
+  BatchProgram P;
+  spider_status st = build_batch(items, &P);
+  if (st != SPIDER_OK) return st;
+  st = enqueue_copies(P, s);
+  if (st != SPIDER_OK || P.m.empty()) return st;
+  const size_t bytes = P.desc.size();
+  std::lock_guard<std::mutex> lk(A.mu);
+  hipError_t e = A.reserve(bytes);
+  if (e != hipSuccess) return hip_fail(e, "batch descriptor buffers");
+  std::memcpy(A.host, P.desc.data(), bytes);
+  e = hipMemcpyAsync(A.dev, A.host, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  st = enqueue_launches(P, A.dev, s);
+  if (st != SPIDER_OK) return st;
   e = hipEventRecord(A.done, s);
   if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
   A.pending = true;
+  return SPIDER_OK;
+}
+
+// ------------------------------------------------------------------ graph-captured batches
+// A batch whose membership (plans, grids, step counts) repeats is captured once as
+// a hipGraph of its kernel launches, with its descriptors in a device buffer of
+// its own, and replayed.  Entries are keyed by every (plan, in, out, steps) of the
+// batch and dropped when one of their plans is destroyed; at most kBatchGraphs
+// entries per process (the oldest is evicted).
+namespace {
+struct BatchGraphEntry {
+  std::vector<std::tuple<const void*, const void*, const void*, int>> key;
+  std::vector<BatchProgram::Copy> copies;
+  hipGraphExec_t exec = nullptr;
+  char* dev_desc = nullptr;
+  int device = 0;
+};
+constexpr size_t kBatchGraphs = 32;
+std::mutex g_bg_mu;
+std::vector<BatchGraphEntry> g_bg;  // oldest first
+std::map<int, hipStream_t> g_bg_capture;  // capture stream per device
+
+void release_entry(BatchGraphEntry& en) {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != en.device) (void)hipSetDevice(en.device);
+  (void)hipDeviceSynchronize();  // a replay may still read the descriptors
+  if (en.exec) hipGraphExecDestroy(en.exec);
+  if (en.dev_desc) hipFree(en.dev_desc);
+  if (cur != en.device) (void)hipSetDevice(cur);
+  en.exec = nullptr;
+  en.dev_desc = nullptr;
+}
+}  // namespace
+
+void batch_graphs_forget_plan(const spider_plan_s* p) {
+  std::lock_guard<std::mutex> lk(g_bg_mu);
+  for (size_t i = 0; i < g_bg.size();) {
+    bool uses = false;
+    for (const auto& k : g_bg[i].key) uses |= std::get<0>(k) == (const void*)p;
+    if (uses) {
+      release_entry(g_bg[i]);
+      g_bg.erase(g_bg.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+static spider_status enqueue_batch_graph(const std::vector<BatchItem>& items, int device, hipStream_t s) {
+  std::vector<std::tuple<const void*, const void*, const void*, int>> key;
+  for (const auto& it : items) key.emplace_back(it.plan, it.in, it.out, it.steps);
+  std::lock_guard<std::mutex> lk(g_bg_mu);
+  BatchGraphEntry* hit = nullptr;
+  for (auto& en : g_bg)
+    if (en.device == device && en.key == key) hit = &en;
+  if (!hit) {
+    BatchProgram P;
+    spider_status st = build_batch(items, &P);
+    if (st != SPIDER_OK) return st;
+    BatchGraphEntry en;
+    en.key = key;
+    en.device = device;
+    en.copies = P.copies;
+    if (!P.m.empty()) {
+      hipError_t e = hipMalloc(&en.dev_desc, P.desc.size());
+      if (e != hipSuccess) return fail(SPIDER_ERR_OOM, "batch graph descriptors: %s", hipGetErrorString(e));
+      e = hipMemcpy(en.dev_desc, P.desc.data(), P.desc.size(), hipMemcpyHostToDevice);
+      hipStream_t& cs = g_bg_capture[device];
+      if (e == hipSuccess && !cs) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        hipFree(en.dev_desc);
+        return hip_fail(e, "batch graph set-up");
+      }
+      st = enqueue_launches(P, en.dev_desc, cs);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(cs, &graph);
+      if (st == SPIDER_OK && e == hipSuccess) e = hipGraphInstantiate(&en.exec, graph, nullptr, nullptr, 0);
+      if (graph) hipGraphDestroy(graph);
+      if (st != SPIDER_OK || e != hipSuccess) {
+        hipFree(en.dev_desc);
+        return st != SPIDER_OK ? st : hip_fail(e, "batch graph capture");
+      }
+    }
+    if (g_bg.size() >= kBatchGraphs) {
+      release_entry(g_bg.front());
+      g_bg.erase(g_bg.begin());
+    }
+    g_bg.push_back(en);
+    hit = &g_bg.back();
+  }
+  // the copies (zero-step results, in == out sources) run eagerly before the replay
+  for (const auto& c : hit->copies) {
+    hipError_t e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  if (hit->exec) {
+    hipError_t e = hipGraphLaunch(hit->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
   return SPIDER_OK;
 }
 
@@ -314,9 +455,14 @@ struct spider_server_s {
   spider_impl::BatchArena arena;
   std::map<size_t, std::vector<void*>> pool;  // idle scratch buffers by size
   size_t pooled = 0;
-  std::vector<double> lat_us;
+  std::vector<double> lat_us;  // ring of the most recent completion latencies
+  size_t lat_next = 0;
+  uint64_t completed = 0;
   double updates = 0.0;
 };
+
+// Latencies kept for the percentiles of spider_server_stats.
+constexpr size_t kLatencyHistory = 1 << 16;
 
 namespace {
 
@@ -340,6 +486,13 @@ void* take_scratch(spider_server_s* S, size_t bytes) {
     }
   }
   void* p = nullptr;
+  if (hipMalloc(&p, bytes) == hipSuccess) return p;
+  // the device is short of memory: return every idle buffer and try once more
+  for (auto& kv : S->pool)
+    for (void* q : kv.second) hipFree(q);
+  S->pool.clear();
+  S->pooled = 0;
+  p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
   return p;
 }
@@ -356,7 +509,13 @@ void finish(spider_server_s* S, ServerRequest* r, spider_status st) {
   const double us =
       std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - r->t_submit).count();
   if (st == SPIDER_OK) {
-    S->lat_us.push_back(us);
+    // latency history: the most recent kLatencyHistory completions (a ring)
+    if (S->lat_us.size() < kLatencyHistory)
+      S->lat_us.push_back(us);
+    else
+      S->lat_us[S->lat_next] = us;
+    S->lat_next = (S->lat_next + 1) % kLatencyHistory;
+    ++S->completed;
     double pts = (double)r->plan->nz * r->plan->ny * r->plan->nx;
     S->updates += pts * r->steps;
   }
@@ -378,7 +537,16 @@ void server_loop(spider_server_s* S) {
         ServerRequest* r = S->queue.front();
         if (S->used + r->footprint > S->budget) break;
         void* scr = take_scratch(S, r->plan->grid_bytes);
-        if (!scr) break;
+        if (!scr) {
+          // nothing running will free memory: the request cannot be served
+          if (S->active.empty()) {
+            S->queue.pop_front();
+            r->done = true;
+            r->result = SPIDER_ERR_OOM;
+            continue;
+          }
+          break;
+        }
         S->queue.pop_front();
         r->scratch = scr;
         S->used += r->footprint;
@@ -460,6 +628,9 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
     }
     items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
+  bool graph = true;
+  for (int i = 0; i < n; ++i) graph = graph && plans[i]->use_graph;
+  if (graph) return enqueue_batch_graph(items, plans[0]->device, static_cast<hipStream_t>(stream));
   return enqueue_batch(global_arena(plans[0]->device), items, static_cast<hipStream_t>(stream));
 }
 
@@ -521,9 +692,16 @@ spider_status spider_poll(spider_server_t S, uint64_t ticket, int* done, spider_
   if (!S || !done) return fail(SPIDER_ERR_INVALID, "bad poll arguments");
   std::lock_guard<std::mutex> lk(S->mu);
   auto it = S->tickets.find(ticket);
-  if (it == S->tickets.end()) return fail(SPIDER_ERR_CLOSED, "unknown ticket %llu", (unsigned long long)ticket);
-  *done = it->second->done ? 1 : 0;
-  if (result) *result = it->second->done ? it->second->result : SPIDER_ERR_NOT_READY;
+  if (it == S->tickets.end())
+    return fail(SPIDER_ERR_CLOSED, "unknown ticket %llu (never issued, or already reported done)",
+                (unsigned long long)ticket);
+  ServerRequest* r = it->second;
+  *done = r->done ? 1 : 0;
+  if (result) *result = r->done ? r->result : SPIDER_ERR_NOT_READY;
+  if (r->done) {  // reported once: the ticket is released
+    S->tickets.erase(it);
+    delete r;
+  }
   return SPIDER_OK;
 }
 
@@ -541,7 +719,7 @@ spider_status spider_server_stats(spider_server_t S, double* p50_us, double* p99
   };
   if (p50_us) *p50_us = pct(0.50);
   if (p99_us) *p99_us = pct(0.99);
-  if (completed) *completed = v.size();
+  if (completed) *completed = S->completed;
   if (stencil_updates) *stencil_updates = S->updates;
   return SPIDER_OK;
 }

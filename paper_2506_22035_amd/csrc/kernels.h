@@ -127,6 +127,10 @@ constexpr int kRowsY3 = 4;
 hipError_t launch_direct(int ndim, int r, int dtype, int zero_taps, const void* in, void* out, int nz, int ny,
                          int nx, const void* coeffs_dev, int seg_h, hipStream_t s);
 
+// Fill n elements of `buf` (dtype: 0 f64, 1 f32, 2 f16, 3 bf16) with pseudo-random
+// values in [0.25, 1) derived from the index and `seed` (the autotuner's timing data).
+hipError_t launch_fill_uniform(void* buf, size_t n, int dtype, uint32_t seed, hipStream_t s);
+
 // Outputs per 2-D band wave strip; strip s covers x in [256 s - 8, 256 s + 248),
 // so a 2-D grid has ceil((nx + 8) / 256) strips.
 constexpr int kStripW = 256;

@@ -405,3 +405,46 @@ hipError_t launch_direct(int ndim, int r, int dtype, int zero_taps, const void* 
 }
 
 }  // namespace spider_impl
+
+// ----------------------------------------------------------------------------- tuning data
+// A field of pseudo-random values in [0.25, 1) (an integer hash of the index and a
+// seed), in the grid's dtype: the autotuner times its candidates on such data
+// rather than on zeros, because the matrix units draw less power on zero
+// operands and the device clocks react to power.
+namespace spider_impl {
+namespace {
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x7feb352dU;
+  h ^= h >> 15;
+  h *= 0x846ca68bU;
+  h ^= h >> 16;
+  return h;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void fill_uniform_kernel(T* buf, size_t n, uint32_t seed) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t h = mix32((uint32_t)i ^ mix32((uint32_t)(i >> 32) + seed));
+    const float v = 0.25f + 0.75f * (float)(h >> 8) * (1.0f / 16777216.0f);
+    buf[i] = (T)v;
+  }
+}
+}  // namespace
+
+hipError_t launch_fill_uniform(void* buf, size_t n, int dtype, uint32_t seed, hipStream_t s) {
+  const dim3 block(256);
+  const size_t want = (n + 255) / 256;
+  const dim3 grid((unsigned)(want < 8192 ? (want > 0 ? want : 1) : 8192));
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL(fill_uniform_kernel<double>, grid, block, 0, s, (double*)buf, n, seed); break;
+    case 1: hipLaunchKernelGGL(fill_uniform_kernel<float>, grid, block, 0, s, (float*)buf, n, seed); break;
+    case 2: hipLaunchKernelGGL(fill_uniform_kernel<_Float16>, grid, block, 0, s, (_Float16*)buf, n, seed); break;
+    case 3: hipLaunchKernelGGL(fill_uniform_kernel<__bf16>, grid, block, 0, s, (__bf16*)buf, n, seed); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace spider_impl

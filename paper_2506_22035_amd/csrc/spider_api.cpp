@@ -721,6 +721,7 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
 
 spider_status spider_plan_destroy(spider_plan_t p) {
   if (!p) return SPIDER_OK;
+  batch_graphs_forget_plan(p);
   for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
   for (auto& kv : p->body_graphs) hipGraphExecDestroy(kv.second);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
@@ -753,6 +754,47 @@ spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* ti
   if (scratch_bytes) *scratch_bytes = p->grid_bytes;
   if (time_block) *time_block = p->engine == SPIDER_ENGINE_DIRECT ? 1 : p->time_block;
   if (tile_h2) *tile_h2 = p->time_block >= 2 ? p->tile_h2 : 0;
+  return SPIDER_OK;
+}
+
+// Matrix instructions of one launch of a paired-line band kernel with a 16-bit
+// carry advancing T steps on grid `g`: each wave (strip x segment) streams
+// ceil(npin / UP) bodies of UP input line pairs, npin = ceil(rows / 2) + T r + T - 1,
+// and every streamed pair costs T passes x 2 halves x (r + 1) pair instructions
+// (one smfmac, or two dense mfma).
+static uint64_t pair_launch_instructions(const spider_plan_s* p, const BandGrid& g, int T) {
+  const int np = p->r + 1, up = np >= 3 ? np : 2 * np;
+  uint64_t iters = 0;
+  for (int s = 0; s < g.nsegs_y; ++s) {
+    const int hrows = std::min(g.seg_h, g.ny - s * g.seg_h);
+    const int npin = (hrows + 1) / 2 + T * p->r + (T - 1);
+    iters += (uint64_t)((npin + up - 1) / up) * up;
+  }
+  const uint64_t per_iter = (uint64_t)T * 2 * np * (p->engine == SPIDER_ENGINE_DENSE ? 2 : 1);
+  return iters * (uint64_t)g.nstrips * per_iter;
+}
+
+spider_status spider_plan_work(spider_plan_t p, int steps, uint64_t* launches, uint64_t* matrix_instructions) {
+  clear_err();
+  if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
+  if (steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
+  const LoopShape L = loop_launches(p, steps);
+  const int total = steps == 0 ? 0 : (p->engine == SPIDER_ENGINE_DIRECT ? steps : L.total);
+  if (launches) *launches = (uint64_t)total;
+  if (!matrix_instructions) return SPIDER_OK;
+  *matrix_instructions = 0;
+  if (p->engine == SPIDER_ENGINE_DIRECT || total == 0) return SPIDER_OK;
+  if (!(p->band_h == 8 && p->carry == p->operand))
+    return fail(SPIDER_ERR_UNSUPPORTED, "matrix instruction counts are kept for paired-line bands with a 16-bit "
+                                        "carry only");
+  uint64_t n = 0;
+  for (int k = 1; k <= total; ++k) {
+    const int kind = L.kind(k);
+    n += kind == 3   ? pair_launch_instructions(p, p->grid_tb2, p->time_block)
+         : kind == 2 ? pair_launch_instructions(p, p->grid_rem2, 2)
+                     : pair_launch_instructions(p, p->grid_template, 1);
+  }
+  *matrix_instructions = n;
   return SPIDER_OK;
 }
 

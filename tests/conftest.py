@@ -15,6 +15,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
-    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
-        oracle.build()
+    oracle.ensure_built()
     return oracle

@@ -18,6 +18,15 @@ def to_dev(x, carry):
     return t.to("cuda:0").contiguous(), host64
 
 
+def host_rounded(x, carry):
+    """The exact fp64 values of host array `x` rounded to the carry dtype (what to_dev
+    places on the device), computed on the host only."""
+    torch = torch_mod()
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[carry]
+    src = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64 if carry == "f64" else np.float32))
+    return src.to(dt).to(torch.float64).numpy()
+
+
 def from_dev(t):
     torch = torch_mod()
     torch.cuda.synchronize()

@@ -15,10 +15,6 @@ from gpu_helpers import empty_like_dev, from_dev, rel_errors, to_dev
 pytestmark = pytest.mark.gpu
 
 TOL = {"f16": (2e-3, 1e-2), "bf16": (3e-2, 6e-2), "f32": (1e-5, 1e-5), "f64": (1e-13, 1e-13)}
-# The 100-step runs at full size: a 16-bit carry rounds every step.  RNE to fp16 of
-# values in [0.5, 1) errs by at most 2^-12 relative (RMS 2^-11 / sqrt(12) ~ 1.4e-4);
-# accumulated coherently over 100 steps: rel-RMS <= 1.4e-2, rel-max <= 2.5e-2.
-TOL_100_STEPS_F16 = (1.4e-2, 2.5e-2)
 LENGTHS = [1, 7, 255, 256, 257, 4096, 10001, 50000, 123457]
 
 
@@ -100,26 +96,6 @@ def test_tile_heights_agree_and_aliasing(oracle_mod):
         plan.apply(y, y, steps)
         assert np.array_equal(from_dev(y), run(plan, xd, steps))
     assert torch.equal(xd, keep)
-
-
-@pytest.mark.parametrize("name", ["1d3p_10240000", "1d5p_10240000"])
-def test_full_size_sampled(oracle_mod, name):
-    # 10 240 000 points, 100 steps, in the benchmark's configuration; the oracle runs
-    # each sampled point on its dependency cone
-    wl = si.workload(name)
-    xd, x64 = to_dev(wl["make_grid"](), "f16")
-    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
-    got = run(plan, xd, wl["steps"])
-    n, h = wl["shape"][0], wl["steps"] * wl["r"]
-    rng = np.random.default_rng(5)
-    pts = [0, 1, n - 1, n - 2, 255, 256, 5119999] + [int(v) for v in rng.integers(0, n, 20)]
-    ref = []
-    for p in pts:
-        a, b = max(0, p - h), min(n, p + h + 1)
-        ref.append(oracle_mod.apply(wl["coeffs"], x64[a:b], wl["steps"])[p - a])
-    rms, mx = rel_errors(np.array([got[p] for p in pts]), np.array(ref))
-    print("%s full size sampled rel-RMS %.3e rel-max %.3e" % (name, rms, mx))
-    assert rms <= TOL_100_STEPS_F16[0] and mx <= TOL_100_STEPS_F16[1]
 
 
 def test_batch_rejects_1d():

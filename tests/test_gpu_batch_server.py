@@ -256,3 +256,95 @@ def test_server_runs_deeply_fused_grids_on_their_own(oracle_mod):
         assert np.array_equal(from_dev(os_), _alone(small, xs, 20))
     finally:
         srv.close()
+
+
+def test_server_holds_plans_and_grids_until_done():
+    # the caller drops its own references to the plan and both grids right after
+    # submitting; the server object keeps them alive until the ticket is done, so
+    # the result is still written to the output and equals the grid alone
+    import gc
+    import weakref
+    import torch
+    wl, xd, _ = _mix()[0]
+    want = _alone(wl, xd, 20)
+    srv = sp.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    try:
+        p = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+        x = xd.clone()
+        o = torch.empty_like(xd)
+        t = srv.submit(p, x, o, 20)
+        wp, wo = weakref.ref(p), weakref.ref(o)
+        out_ptr = o.data_ptr()
+        del p, x, o
+        gc.collect()
+        assert wp() is not None and wo() is not None
+        _wait(srv, [t])
+        o = wo()
+        assert o is not None and o.data_ptr() == out_ptr
+        assert np.array_equal(from_dev(o), want)
+        del o
+        gc.collect()
+        assert wp() is None and wo() is None
+    finally:
+        srv.close()
+
+
+def test_server_releases_a_ticket_once_reported_done():
+    import ctypes
+    import torch
+    wl, xd, _ = _mix()[1]
+    srv = sp.Server(hbm_budget_bytes=1 << 30, max_slots=4)
+    try:
+        p = sp.Plan(wl["coeffs"], wl["shape"], carry="f16")
+        o = torch.empty_like(xd)
+        t = srv.submit(p, xd, o, 3)
+        _wait(srv, [t])
+        # the library reported it done once; a second poll of the C ABI finds no ticket
+        d, r = ctypes.c_int(), ctypes.c_int()
+        assert sp.lib().spider_poll(srv._h, ctypes.c_uint64(t), ctypes.byref(d), ctypes.byref(r)) == 7
+        # the binding keeps the status it was told
+        assert srv.poll(t) == (True, 0)
+    finally:
+        srv.close()
+
+
+def test_batch_graph_replays_equal_direct_launches():
+    # plans with use_graph capture a batch of fixed membership once and replay it; the
+    # replays must equal the directly launched batch bit for bit, also after eager
+    # work on the same buffers between replays, with in-place and zero-step entries,
+    # and after a plan of the batch is destroyed and replaced
+    import torch
+    mix = _mix()
+    steps = [wl["steps"] for wl, _, _ in mix]
+    steps[1], steps[3] = 3, 0
+    plans_d = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", use_graph=False) for wl, _, _ in mix]
+    outs_d = [torch.empty_like(xd) for _, xd, _ in mix]
+    ins = [xd for _, xd, _ in mix]
+    sp.apply_batch(plans_d, ins, outs_d, steps)
+    want = [from_dev(o) for o in outs_d]
+    plans_g = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16") for wl, _, _ in mix]
+    outs_g = [torch.empty_like(xd) for _, xd, _ in mix]
+    for rep in range(3):
+        sp.apply_batch(plans_g, ins, outs_g, steps)
+        torch.cuda.synchronize()
+        for o, w in zip(outs_g, want):
+            assert np.array_equal(from_dev(o), w), rep
+        for o in outs_g:        # eager work on the outputs between replays
+            o.zero_()
+        plans_g[0].apply(ins[0], outs_g[0], 2)
+        torch.cuda.synchronize()
+    # in place: each input copied, then advanced in its own buffer
+    for rep in range(2):
+        bufs = [x.clone() for x in ins]
+        sp.apply_batch(plans_g, bufs, bufs, steps)
+        torch.cuda.synchronize()
+        for b, w in zip(bufs, want):
+            assert np.array_equal(from_dev(b), w), ("in place", rep)
+    # a destroyed plan's graphs are dropped; its replacement computes afresh
+    wl0 = mix[0][0]
+    plans_g[0].close()
+    plans_g[0] = sp.Plan(wl0["coeffs"], wl0["shape"], carry="f16")
+    sp.apply_batch(plans_g, ins, outs_g, steps)
+    torch.cuda.synchronize()
+    for o, w in zip(outs_g, want):
+        assert np.array_equal(from_dev(o), w)

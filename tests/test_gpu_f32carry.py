@@ -138,23 +138,6 @@ def test_tile_heights_and_aliasing(oracle_mod):
     assert torch.equal(xd, keep)
 
 
-def test_full_size_box2d49p_sampled(oracle_mod):
-    # the headline workload at full size with the fp32 carry and split 3, as the benchmark runs it
-    from test_gpu_parity import _cone_samples
-    wl = si.workload("box2d49p_10240")
-    xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
-    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3)
-    got = run(plan, xd, wl["steps"])
-    rng = np.random.default_rng(1)
-    n = wl["shape"][0]
-    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (7, 3000), (n // 2, n // 3)]
-    pts += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(10)]
-    ref = _cone_samples(oracle_mod, wl["coeffs"], x64, wl["steps"], pts)
-    rms, mx = rel_errors(np.array([got[p] for p in pts]), ref)
-    print("full-size f32 carry split 3 sampled rel-RMS %.3e rel-max %.3e" % (rms, mx))
-    assert rms <= TOL3["f16"][0] and mx <= TOL3["f16"][1]
-
-
 def test_batch_and_server_reject_f32_carry():
     import torch
     w = np.ones((3, 3)) / 9

@@ -252,27 +252,6 @@ def _cone_samples(oracle_mod, w, x64, steps, pts):
     return np.array(out)
 
 
-@pytest.mark.parametrize("carry", ["f16", "bf16"])
-def test_full_size_box2d49p_sampled(oracle_mod, carry):
-    # the headline workload at full size (10240^2, 50 steps) in the benchmark's launch
-    # configuration; the oracle computes sampled points on their dependency cones
-    wl = si.workload("box2d49p_10240")
-    xd, x64 = to_dev(wl["make_grid"](), carry)
-    plan = sp.Plan(wl["coeffs"], wl["shape"], carry=carry)
-    got = run(plan, xd, wl["steps"])
-    rng = np.random.default_rng(0)
-    n = wl["shape"][0]
-    pts = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0), (5, 5000), (n // 2, n // 2)]
-    pts += [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(10)]
-    ref = _cone_samples(oracle_mod, wl["coeffs"], x64, wl["steps"], pts)
-    g = np.array([got[p] for p in pts])
-    rms, mx = rel_errors(g, ref)
-    print("full-size %s sampled rel-RMS %.3e rel-max %.3e" % (carry, rms, mx))
-    tr, tm = TOL[(carry, 2)]
-    assert rms <= tr and mx <= tm
-    assert np.isfinite(got).all()
-
-
 # ------------------------------------------------------------------ 3-D
 
 SHAPES_3D = [(9, 10, 300), (5, 7, 257), (1, 1, 1), (20, 9, 520), (3, 4, 8)]
