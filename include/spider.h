@@ -54,7 +54,7 @@ typedef enum { SPIDER_F64 = 0, SPIDER_F32 = 1, SPIDER_F16 = 2, SPIDER_BF16 = 3 }
 typedef enum {
     SPIDER_ENGINE_AUTO = 0,   /* sparse for 16-bit carries, direct otherwise */
     SPIDER_ENGINE_SPARSE = 1, /* strided swap + v_smfmac on 16-bit operands; the carry is the
-                                 operand type, or fp32 (2-D) with operands split from it */
+                                 operand type, or fp32 with operands split from it */
     SPIDER_ENGINE_DENSE = 2,  /* same band and gather on dense v_mfma (16-bit operands) */
     SPIDER_ENGINE_DIRECT = 3  /* plain neighbour sum on the vector ALUs (fp32 / fp64 carries) */
 } spider_engine;
@@ -133,8 +133,8 @@ spider_status spider_opts_default(spider_opts* o);
  * them to the current HIP device.  A grid-sized scratch buffer is allocated on the
  * first spider_apply / spider_apply_batch (or at plan time when autotuning).
  * Errors: INVALID (arguments; on the matrix engines also a coefficient whose 16-bit
- * rounding overflows, |w| > 65504 for fp16), UNSUPPORTED (e.g. a matrix engine with an fp64 carry,
- * or with an fp32 carry on a 3-D grid), OOM, HIP.  The plan is immutable after
+ * rounding overflows, |w| > 65504 for fp16), UNSUPPORTED (e.g. a matrix engine with an fp64 carry),
+ * OOM, HIP.  The plan is immutable after
  * creation and owns its device memory.
  */
 spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, int radius,

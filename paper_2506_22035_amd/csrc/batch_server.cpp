@@ -423,6 +423,15 @@ static BatchArena& global_arena(int device) {
 
 // =========================================================================== server
 
+namespace {
+// Plans that batches and the server run with their own launches: the matrix
+// engines with an fp32 carry (the batched kernel holds 16-bit bodies only).
+bool runs_alone(const spider_plan_s* p) {
+  return p->carry == SPIDER_F32 && p->engine != SPIDER_ENGINE_DIRECT && p->ndim >= 2;
+}
+}  // namespace
+
+
 struct ServerRequest {
   uint64_t ticket = 0;
   spider_plan_s* plan = nullptr;
@@ -572,7 +581,7 @@ void server_loop(spider_server_s* S) {
     for (ServerRequest* r : round) {
       const int k = std::min(r->remaining, S->round_steps);
       const spider_impl::BatchItem it{r->plan, r->started ? r->out : r->in, r->out, r->scratch, k};
-      if (r->plan->time_block > 2 && r->plan->ndim == 2)
+      if ((r->plan->time_block > 2 && r->plan->ndim == 2) || runs_alone(r->plan))
         solo.push_back(it);
       else
         groups[(r->plan->operand * 8 + r->plan->engine) * 4 + r->plan->ndim].push_back(it);
@@ -615,6 +624,7 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
   clear_err();
   if (n < 1 || n > 4096 || !plans || !ins || !outs || !steps) return fail(SPIDER_ERR_INVALID, "bad batch arguments");
   std::vector<BatchItem> items;
+  std::vector<int> solo;
   for (int i = 0; i < n; ++i) {
     if (!plans[i] || !ins[i] || !outs[i]) return fail(SPIDER_ERR_INVALID, "NULL plan or grid in batch entry %d", i);
     spider_status dev_st = check_device(plans[i]);
@@ -626,12 +636,26 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
       spider_status st = ensure_scratch(plans[i]);
       if (st != SPIDER_OK) return st;
     }
-    items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
+    if (steps[i] < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0 (batch entry %d)", i);
+    if (runs_alone(plans[i]))
+      solo.push_back(i);
+    else
+      items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
-  bool graph = true;
-  for (int i = 0; i < n; ++i) graph = graph && plans[i]->use_graph;
-  if (graph) return enqueue_batch_graph(items, plans[0]->device, static_cast<hipStream_t>(stream));
-  return enqueue_batch(global_arena(plans[0]->device), items, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!items.empty()) {
+    bool graph = true;
+    for (const auto& it : items) graph = graph && it.plan->use_graph;
+    spider_status st = graph ? enqueue_batch_graph(items, items[0].plan->device, s)
+                             : enqueue_batch(global_arena(items[0].plan->device), items, s);
+    if (st != SPIDER_OK) return st;
+  }
+  // fp32-carry grids run their own time loops on the same stream (as spider_apply)
+  for (int i : solo) {
+    spider_status st = spider_apply(plans[i], ins[i], outs[i], steps[i], stream);
+    if (st != SPIDER_OK) return st;
+  }
+  return SPIDER_OK;
 }
 
 spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue, spider_server_t* out) {
@@ -659,10 +683,11 @@ spider_status spider_submit(spider_server_t S, spider_plan_t plan, const void* i
                             uint64_t* ticket) {
   clear_err();
   if (!S || !plan || !in || !out || !ticket || steps < 0) return fail(SPIDER_ERR_INVALID, "bad submit arguments");
-  if (plan->engine == SPIDER_ENGINE_DIRECT || plan->carry != plan->operand || plan->ndim == 1 ||
-      (plan->ndim == 2 ? plan->r > 3 : plan->r != 1) || plan->row_swap)
+  if (!runs_alone(plan) && (plan->engine == SPIDER_ENGINE_DIRECT || plan->carry != plan->operand ||
+                            plan->ndim == 1 || (plan->ndim == 2 ? plan->r > 3 : plan->r != 1) || plan->row_swap))
     return fail(SPIDER_ERR_UNSUPPORTED,
-                "the server runs 16-bit plans with the implicit row swap: 2-D radius 1..3, 3-D radius 1");
+                "the server runs matrix-engine plans: 16-bit plans with the implicit row swap (2-D radius 1..3, "
+                "3-D radius 1) and fp32-carry plans (2-D, 3-D)");
   if (plan->device != S->device)
     return fail(SPIDER_ERR_INVALID, "the plan was built on device %d, the server runs on device %d", plan->device,
                 S->device);

@@ -85,6 +85,15 @@ int band2d_pair_tbt_blocks_per_cu(int r, int operand, int engine, int T);
 hipError_t launch_band2d_pair_f32(int r, int operand, int engine, bool xlo, int T, const BandGrid& g,
                                   hipStream_t s);
 int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, int T);
+// 1-D band engine on fp32 lines: the 16-bit 1-D decomposition (256-point blocks,
+// seg_h blocks per wave) with 16-bit operands split from the fp32 values (x_hi, and
+// x_lo when `xlo`), fp32 stores; one step per launch.
+hipError_t launch_band1d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s);
+// 3-D (radius 1) band engine on fp32 grids: the 16-bit 3-D decomposition (strips of
+// 256 points, kRowsY3 lines per plane block, seg_h planes per wave) with 16-bit
+// operands split from the fp32 values (x_hi, and x_lo when `xlo`), fp32 stores.
+hipError_t launch_band3d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s);
+int band3d_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, uint32_t rowmask);
 
 // 1-D band engine: the line is cut into nstrips = ceil((nx + 8) / 256) blocks of 256
 // outputs at x0 = 256 j - 8; each wave streams seg_h consecutive blocks (nblocks =

@@ -1,4 +1,4 @@
-// 2-D band engine with an fp32 carry.
+// 1-D, 2-D and 3-D band engines with an fp32 carry.
 //
 // The grid is kept in fp32 between steps (8 bytes of HBM traffic per
 // point-step).  On load, every input value x is split into 16-bit operands
@@ -206,6 +206,286 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((R <= 3 && E
   band2d_f32_body<R, OP, ENG, ALIGNED, XLO>(g, w, lds);
 }
 
+// ----------------------------------------------------------------------------- 1-D
+// The 1-D band engine with an fp32 carry: the line is cut into 256-point blocks
+// (block k at x0 = 256 k - 8, its window row covering [x0 - 8, x0 + 264) of the
+// same array, zero only beyond the ends), each staged as hi (and lo, XLO)
+// 16-bit LDS rows in the padded layout; the single kernel row takes one
+// instruction per row part, and the fp32 sums are stored without rounding.  A
+// wave streams seg_h consecutive blocks, staging U blocks ahead.
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO>
+__device__ __forceinline__ void band1d_f32_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int U = 8;
+  constexpr int NS = XLO ? 2 : 1;  // LDS rows per block
+  const int lane = threadIdx.x;
+  const int b0 = w * g.seg_h;
+  const int nb = min(g.seg_h, g.nstrips - b0);
+  const int nx = g.nx;
+  const u32x4 A0 = (ENG == 1) ? reinterpret_cast<const u32x4*>(g.apack)[lane] : (u32x4){0, 0, 0, 0};
+  const u32x4 Dh = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 0];
+  const u32x4 Dl = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 1];
+  const uint32_t I0 = (ENG == 1) ? g.ipack[lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const __amdgpu_buffer_rsrc_t rin =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * 4, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * 4, kRsrcWord3);
+  const int mw = lds_phys(2 * lane);
+  const int tw_line = lds_phys(128 + (lane >> 1)) * 4 + 2 * (lane & 1);
+  const int spare_tw = (U * NS * kLdsRowDw) * 4;
+  auto load_blk = [&](int j) {  // block b0 + j (nothing beyond the segment); negative x wraps out of range
+    const int x0 = 256 * (b0 + j) - 8;
+    const bool v = j < nb;
+    const uint32_t mvoff = v ? (uint32_t)((x0 - 8 + 4 * lane) * 4) : kOffNone;
+    const uint32_t tvoff = (v && lane < 16) ? (uint32_t)((x0 + 248 + lane) * 4) : kOffNone;
+    return load_f32_line<ALIGNED>(rin, mvoff, tvoff);
+  };
+  auto out_off = [&](int j) {
+    const int x = 256 * (b0 + j) - 8 + 16 * (lane & 15) + 4 * (lane >> 4);
+    return (j < nb && x >= 0) ? (uint32_t)(x * 4) : kOffNone;
+  };
+  F32Line stg[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) stg[q] = load_blk(q);
+  f32x4 done[U];
+  const int nbody = (nb + U - 1) / U;
+  for (int jb = 0; jb < nbody * U; jb += U) {
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      uint32_t* hl = lds + q * NS * kLdsRowDw;
+      const int tw = lane < 16 ? tw_line + q * NS * kLdsRowDw * 4 : spare_tw;
+      uint32_t h0, l0, h1, l1, th, tl;
+      split2<OP, XLO>(stg[q].m.x, stg[q].m.y, &h0, &l0);
+      split2<OP, XLO>(stg[q].m.z, stg[q].m.w, &h1, &l1);
+      split2<OP, XLO>(stg[q].t, 0u, &th, &tl);
+      *reinterpret_cast<uint2*>(hl + mw) = make_uint2(h0, h1);
+      *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + tw) = (uint16_t)th;
+      if constexpr (XLO) {
+        *reinterpret_cast<uint2*>(hl + kLdsRowDw + mw) = make_uint2(l0, l1);
+        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + tw + (lane < 16 ? kLdsRowDw * 4 : 0)) =
+            (uint16_t)tl;
+      }
+    }
+    if (jb > 0) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) store_f32x4<ALIGNED>(rout, out_off(jb - U + q), done[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) stg[q] = load_blk(jb + U + q);
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const uint32_t* hrow = lds + q * NS * kLdsRowDw;
+      const u32x4 bh = {hrow[p1], hrow[p1 + 10], hrow[p2], hrow[p2 + 10]};
+      f32x4 acc = band_mma<OP, ENG, 0>((f32x4){0.f, 0.f, 0.f, 0.f}, A0, Dh, Dl, I0, bh);
+      if constexpr (XLO) {
+        const uint32_t* lrow = hrow + kLdsRowDw;
+        const u32x4 bl = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+        acc = band_mma<OP, ENG, 0>(acc, A0, Dh, Dl, I0, bl);
+      }
+      done[q] = acc;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) store_f32x4<ALIGNED>(rout, out_off(nbody * U - U + q), done[q]);
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XLO ? 2 : 3))) void band1d_f32_kernel(BandGrid g) {
+  __shared__ uint32_t lds[8 * (XLO ? 2 : 1) * kLdsRowDw + 64];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band1d_f32_body<R, OP, ENG, ALIGNED, XLO>(g, w, lds);
+}
+
+// ----------------------------------------------------------------------------- 3-D
+// The 3-D band engine (radius 1) with an fp32 carry: the decomposition of the
+// 16-bit 3-D kernel (a wave owns a 256-point strip, kRowsY3 output lines and a
+// segment of planes, streams input planes once through 2r + 1 rotating plane
+// accumulators; kernel row (dz, dy) is packed as row dz (2r + 1) + dy), with
+// every input line split on load into hi (and lo, XLO) 16-bit LDS lines as in the
+// 2-D kernel above, two products per kernel row with the split, and fp32 stores.
+// Output planes are accumulated over (dz, dy) in a fixed order, hi before lo,
+// independent of the segmentation.
+template <uint32_t MASK, int R>
+constexpr bool row_used3(int a) {
+  return (MASK >> a) & 1u;
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, uint32_t MASK>
+__device__ __forceinline__ void band3d_f32_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int NR = RR * RR;
+  constexpr int YB = kRowsY3;
+  constexpr int NLY = YB + 2 * R;      // input lines per plane
+  constexpr int NS = XLO ? 2 : 1;      // LDS lines per input line
+  const int lane = threadIdx.x;
+  int t = w;
+  const int strip = t % g.nstrips;
+  t /= g.nstrips;
+  const int sy = t % g.nsegs_y, sz = t / g.nsegs_y;
+  const int x0 = strip * kStripW, yb0 = sy * YB, z0 = sz * g.seg_h;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int hz = min(g.seg_h, nz - z0);
+  const int npl = ((hz + 2 * R + RR - 1) / RR) * RR;  // planes streamed, padded to RR
+
+  u32x4 A[NR], Dh[NR], Dl[NR];
+  uint32_t I[(NR + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < NR; ++a) {
+    if constexpr (ENG == 1) {
+      A[a] = row_used3<MASK, R>(a) ? reinterpret_cast<const u32x4*>(g.apack)[a * 64 + lane] : (u32x4){0, 0, 0, 0};
+      Dh[a] = Dl[a] = (u32x4){0, 0, 0, 0};
+    } else {
+      A[a] = (u32x4){0, 0, 0, 0};
+      Dh[a] = row_used3<MASK, R>(a) ? reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 0]
+                                    : (u32x4){0, 0, 0, 0};
+      Dl[a] = row_used3<MASK, R>(a) ? reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 1]
+                                    : (u32x4){0, 0, 0, 0};
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < (NR + 1) / 2; ++a) I[a] = (ENG == 1) ? g.ipack[a * 64 + lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  // the 16-bit kernel's strip starts at x0 and its staged row covers [x0 - 8, x0 + 264):
+  // lane l loads x0 - 8 + 4l .. +3, lanes 0..15 also x0 + 248 + l
+  const uint32_t mvoff = (uint32_t)((x0 - 8 + 4 * lane) * 4);
+  const uint32_t tvoff = lane < 16 ? (uint32_t)((x0 + 248 + lane) * 4) : kOffNone;
+  const uint32_t ovoff = (uint32_t)((x0 + 16 * (lane & 15) + 4 * (lane >> 4)) * 4);
+  const int spare_tw = (NLY * NS * kLdsRowDw) * 4;
+  const int mw = lds_phys(2 * lane);
+  const int tw_line = lds_phys(128 + (lane >> 1)) * 4 + 2 * (lane & 1);
+
+  // Planes are staged in order: plane pj is z = z0 - R + pj; its NLY lines y = yb0 - R + l.
+  const int lb = nx * 4;
+  const int64_t pbytes = (int64_t)ny * lb;
+  uint64_t in_addr = reinterpret_cast<uint64_t>(g.in) + ((int64_t)(z0 - R) * ny + (yb0 - R)) * lb;
+  const int zlo = max(0, z0 - R), zhi = min(nz, z0 + hz + R);
+  int zrel = z0 - R - zlo;
+  const uint32_t zspan = zhi > zlo ? (uint32_t)(zhi - zlo) : 0u;
+  F32Line stg[NLY];
+  auto stage = [&]() {
+    const bool zv = (uint32_t)zrel < zspan;
+#pragma unroll
+    for (int l = 0; l < NLY; ++l) {
+      const bool valid = zv && (uint32_t)(yb0 - R + l) < (uint32_t)ny;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          reinterpret_cast<void*>(in_addr + (uint64_t)(l * lb)), (short)0, valid ? lb : 0, kRsrcWord3);
+      stg[l] = load_f32_line<ALIGNED>(rs, mvoff, tvoff);
+    }
+    in_addr += (uint64_t)pbytes;
+    ++zrel;
+  };
+  uint64_t out_addr = reinterpret_cast<uint64_t>(g.out) + ((int64_t)z0 * ny + yb0) * lb;
+  auto store_plane = [&](int k, const f32x4* vals) {
+#pragma unroll
+    for (int b = 0; b < YB; ++b) {
+      const bool ov = k < hz && yb0 + b < ny;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          reinterpret_cast<void*>(out_addr + (uint64_t)(b * lb)), (short)0, ov ? lb : 0, kRsrcWord3);
+      store_f32x4<ALIGNED>(rs, ovoff, vals[b]);
+    }
+    out_addr += (uint64_t)pbytes;
+  };
+  stage();
+  f32x4 acc[RR][YB];
+#pragma unroll
+  for (int s2 = 0; s2 < RR; ++s2)
+#pragma unroll
+    for (int b = 0; b < YB; ++b) acc[s2][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  f32x4 done[YB];
+  int done_plane = -1;
+
+  for (int pb = 0; pb < npl; pb += RR) {
+#pragma unroll
+    for (int q = 0; q < RR; ++q) {
+      const int pj = pb + q;
+      wave_lds_sync();
+#pragma unroll
+      for (int l = 0; l < NLY; ++l) {
+        uint32_t* hl = lds + l * NS * kLdsRowDw;
+        const int tw = lane < 16 ? tw_line + l * NS * kLdsRowDw * 4 : spare_tw;
+        uint32_t h0, l0, h1, l1, th, tl;
+        split2<OP, XLO>(stg[l].m.x, stg[l].m.y, &h0, &l0);
+        split2<OP, XLO>(stg[l].m.z, stg[l].m.w, &h1, &l1);
+        split2<OP, XLO>(stg[l].t, 0u, &th, &tl);
+        *reinterpret_cast<uint2*>(hl + mw) = make_uint2(h0, h1);
+        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + tw) = (uint16_t)th;
+        if constexpr (XLO) {
+          *reinterpret_cast<uint2*>(hl + kLdsRowDw + mw) = make_uint2(l0, l1);
+          *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + tw + (lane < 16 ? kLdsRowDw * 4 : 0)) =
+              (uint16_t)tl;
+        }
+      }
+      if (done_plane >= 0) store_plane(done_plane, done);
+      stage();  // plane pj + 1
+      wave_lds_sync();
+#pragma unroll
+      for (int l = 0; l < NLY; ++l) {
+        const uint32_t* hrow = lds + l * NS * kLdsRowDw;
+        const u32x4 bh = {hrow[p1], hrow[p1 + 10], hrow[p2], hrow[p2 + 10]};
+        u32x4 bl = {0u, 0u, 0u, 0u};
+        if constexpr (XLO) {
+          const uint32_t* lrow = hrow + kLdsRowDw;
+          bl = (u32x4){lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+        }
+#pragma unroll
+        for (int dz = 0; dz < RR; ++dz) {
+          const int slot = ((q - dz) % RR + RR) % RR;  // output plane pj - dz
+#pragma unroll
+          for (int b = 0; b < YB; ++b) {
+            const int dy = l - b;  // input line yb0 - R + l feeds output line yb0 + b
+            if (dy < 0 || dy >= RR) continue;
+            const int a = dz * RR + dy;
+            if (!row_used3<MASK, R>(a)) continue;
+            if (a & 1) {
+              acc[slot][b] = band_mma<OP, ENG, 1>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bh);
+              if constexpr (XLO) acc[slot][b] = band_mma<OP, ENG, 1>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bl);
+            } else {
+              acc[slot][b] = band_mma<OP, ENG, 0>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bh);
+              if constexpr (XLO) acc[slot][b] = band_mma<OP, ENG, 0>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bl);
+            }
+          }
+        }
+      }
+      // output plane pj - 2R is complete
+      const int fs = (q + 1) % RR;
+#pragma unroll
+      for (int b = 0; b < YB; ++b) {
+        done[b] = acc[fs][b];
+        acc[fs][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      }
+      done_plane = pj - 2 * R;
+    }
+  }
+  if (done_plane >= 0) store_plane(done_plane, done);
+}
+
+template <int R>
+constexpr uint32_t box_mask3_f32() {
+  return (1u << ((2 * R + 1) * (2 * R + 1))) - 1u;
+}
+template <int R>
+constexpr uint32_t star_mask3_f32() {
+  uint32_t m = 0;
+  for (int dz = 0; dz <= 2 * R; ++dz)
+    for (int dy = 0; dy <= 2 * R; ++dy)
+      if (dz == R || dy == R) m |= 1u << (dz * (2 * R + 1) + dy);
+  return m;
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, uint32_t MASK>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void band3d_f32_kernel(BandGrid g) {
+  constexpr int NLY = kRowsY3 + 2 * R;
+  __shared__ uint32_t lds[NLY * (XLO ? 2 : 1) * kLdsRowDw + 64];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band3d_f32_body<R, OP, ENG, ALIGNED, XLO, MASK>(g, w, lds);
+}
+
 namespace {
 
 template <int OP, int ENG, bool AL, bool XLO>
@@ -239,6 +519,86 @@ hipError_t launch_band2d_f32(int r, int operand, int engine, bool xlo, const Ban
   if (operand == 3 && engine == 1) return dispatch_f32_al<3, 1>(r, xlo, g, s);
   if (operand == 3 && engine == 2) return dispatch_f32_al<3, 2>(r, xlo, g, s);
   return hipErrorInvalidValue;
+}
+
+namespace {
+template <int OP, int ENG, bool AL, bool XLO>
+hipError_t dispatch3d_f32(const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  if ((g.rowmask & ~star_mask3_f32<1>()) == 0)  // every non-zero row lies on the star
+    hipLaunchKernelGGL((band3d_f32_kernel<1, OP, ENG, AL, XLO, star_mask3_f32<1>()>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((band3d_f32_kernel<1, OP, ENG, AL, XLO, box_mask3_f32<1>()>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+template <int OP, int ENG>
+hipError_t dispatch3d_f32_al(bool xlo, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 4) == 0;
+  if (al) return xlo ? dispatch3d_f32<OP, ENG, true, true>(g, s) : dispatch3d_f32<OP, ENG, true, false>(g, s);
+  return xlo ? dispatch3d_f32<OP, ENG, false, true>(g, s) : dispatch3d_f32<OP, ENG, false, false>(g, s);
+}
+template <int OP, int ENG, bool XLO>
+int occ3d_f32(uint32_t rowmask) {
+  int nb = 0;
+  hipError_t e;
+  if ((rowmask & ~star_mask3_f32<1>()) == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band3d_f32_kernel<1, OP, ENG, true, XLO, star_mask3_f32<1>()>,
+                                                     64, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band3d_f32_kernel<1, OP, ENG, true, XLO, box_mask3_f32<1>()>,
+                                                     64, 0);
+  return e == hipSuccess ? nb : 0;
+}
+}  // namespace
+
+namespace {
+template <int OP, int ENG, bool AL, bool XLO>
+hipError_t dispatch1d_f32(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  switch (r) {
+    case 1: hipLaunchKernelGGL((band1d_f32_kernel<1, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band1d_f32_kernel<2, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band1d_f32_kernel<3, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    case 4: hipLaunchKernelGGL((band1d_f32_kernel<4, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    case 5: hipLaunchKernelGGL((band1d_f32_kernel<5, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    case 6: hipLaunchKernelGGL((band1d_f32_kernel<6, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    case 7: hipLaunchKernelGGL((band1d_f32_kernel<7, OP, ENG, AL, XLO>), grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template <int OP, int ENG>
+hipError_t dispatch1d_f32_al(int r, bool xlo, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 4) == 0;
+  if (al) return xlo ? dispatch1d_f32<OP, ENG, true, true>(r, g, s) : dispatch1d_f32<OP, ENG, true, false>(r, g, s);
+  return xlo ? dispatch1d_f32<OP, ENG, false, true>(r, g, s) : dispatch1d_f32<OP, ENG, false, false>(r, g, s);
+}
+}  // namespace
+
+hipError_t launch_band1d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s) {
+  if (operand == 2 && engine == 1) return dispatch1d_f32_al<2, 1>(r, xlo, g, s);
+  if (operand == 2 && engine == 2) return dispatch1d_f32_al<2, 2>(r, xlo, g, s);
+  if (operand == 3 && engine == 1) return dispatch1d_f32_al<3, 1>(r, xlo, g, s);
+  if (operand == 3 && engine == 2) return dispatch1d_f32_al<3, 2>(r, xlo, g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_band3d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s) {
+  if (r != 1) return hipErrorInvalidValue;
+  if (operand == 2 && engine == 1) return dispatch3d_f32_al<2, 1>(xlo, g, s);
+  if (operand == 2 && engine == 2) return dispatch3d_f32_al<2, 2>(xlo, g, s);
+  if (operand == 3 && engine == 1) return dispatch3d_f32_al<3, 1>(xlo, g, s);
+  if (operand == 3 && engine == 2) return dispatch3d_f32_al<3, 2>(xlo, g, s);
+  return hipErrorInvalidValue;
+}
+
+int band3d_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, uint32_t rowmask) {
+  if (r != 1) return 0;
+  if (operand == 2 && engine == 1) return xlo ? occ3d_f32<2, 1, true>(rowmask) : occ3d_f32<2, 1, false>(rowmask);
+  if (operand == 2 && engine == 2) return xlo ? occ3d_f32<2, 2, true>(rowmask) : occ3d_f32<2, 2, false>(rowmask);
+  if (operand == 3 && engine == 1) return xlo ? occ3d_f32<3, 1, true>(rowmask) : occ3d_f32<3, 1, false>(rowmask);
+  if (operand == 3 && engine == 2) return xlo ? occ3d_f32<3, 2, true>(rowmask) : occ3d_f32<3, 2, false>(rowmask);
+  return 0;
 }
 
 int band2d_f32_blocks_per_cu(int r, int operand, int engine, bool xlo) {

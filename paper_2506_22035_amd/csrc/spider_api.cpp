@@ -98,7 +98,9 @@ static int auto_tile_h_3d(const spider_plan_s* p) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
-  int per_cu = band3d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0, p->rowmask);
+  int per_cu = p->carry == SPIDER_F32
+                   ? band3d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, p->rowmask)
+                   : band3d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0, p->rowmask);
   if (per_cu <= 0) per_cu = 8;
   const long long slots = (long long)ncu * per_cu;
   const long long cols = (long long)((p->nx + kStripW - 1) / kStripW) * ((p->ny + kRowsY3 - 1) / kRowsY3);
@@ -148,7 +150,8 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
     BandGrid g = p->grid_template;
     g.in = src;
     g.out = dst;
-    e = launch_band1d(p->r, p->operand, p->engine, g, s);
+    e = p->carry == SPIDER_F32 ? launch_band1d_f32(p->r, p->operand, p->engine, p->split == 3, g, s)
+                               : launch_band1d(p->r, p->operand, p->engine, g, s);
   } else if (p->band_h == 8) {
     BandGrid g = p->grid_template;
     g.in = src;
@@ -170,7 +173,8 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
     BandGrid g = p->grid_template;
     g.in = src;
     g.out = dst;
-    e = launch_band3d(p->r, p->operand, p->engine, nullptr, &g, 1, s);
+    e = p->carry == SPIDER_F32 ? launch_band3d_f32(p->r, p->operand, p->engine, p->split == 3, g, s)
+                               : launch_band3d(p->r, p->operand, p->engine, nullptr, &g, 1, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SPIDER_OK;
@@ -506,8 +510,6 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     return fail(SPIDER_ERR_UNSUPPORTED,
                 "the matrix engines take 16-bit operands (gfx950 has no fp64 structured-sparse instruction); "
                 "use the direct engine for fp64 grids");
-  if (matrix && o.carry == SPIDER_F32 && ndim != 2)
-    return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines with an fp32 carry run 2-D grids only");
   if (engine == SPIDER_ENGINE_DIRECT && low)
     return fail(SPIDER_ERR_UNSUPPORTED, "the direct engine runs fp32/fp64 grids only");
   if (matrix && (o.split < 1 || o.split > 3 || (o.split == 3 && low)))

@@ -105,3 +105,66 @@ def test_batch_rejects_1d():
     with pytest.raises(sp.SpiderError) as e:
         sp.apply_batch([plan], [x], [torch.empty_like(x)], [3])
     assert e.value.status == 2
+
+
+# ------------------------------------------------------------------ fp32 carry on the matrix engines
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("n", [1, 7, 255, 256, 257, 4099, 50000])
+def test_f32_carry_integer_exact_input_split(oracle_mod, operand, engine, n):
+    # all-ones taps (r = 1) on inputs in {1, 2}: the inputs of the ninth step reach ~1.3e4,
+    # beyond the 16-bit significand but exact as x_hi + x_lo; outputs exact in fp32.
+    # Integer taps of radius up to 7 with mixed signs over fewer steps.
+    cases = [(np.ones(3), 9, (1, 2))]
+    cases += [(si.integer_coeffs(1, r, -1, 1, 30 + r), 3, (-2, 2)) for r in (1, 3, 7)]
+    for w, steps, (lo, hi) in cases:
+        x = si.grid_integer((n,), lo, hi, 90 + n % 13)
+        xd, x64 = to_dev(x, "f32")
+        plan = sp.Plan(w, (n,), carry="f32", engine=engine, split=3, operand=operand)
+        assert plan.info()["engine"] == engine
+        ref = oracle_mod.apply(w, x64, steps)
+        assert np.abs(oracle_mod.apply(w, x64, steps - 1)).max() < 65504
+        got = run(plan, xd, steps)
+        assert np.array_equal(got, ref), (w.shape, steps, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("operand", ["f16", "bf16"])
+def test_f32_carry_without_split_equals_16bit_carry(operand):
+    # without the input split the arithmetic is the 16-bit carry's: one step rounded to
+    # 16 bits equals the 16-bit plan's step bit for bit
+    import torch
+    wl = si.workload("1d5p_10240000", small=True)
+    x16, _ = to_dev(wl["make_grid"](), operand)
+    x32 = x16.to(torch.float32)
+    p16 = sp.Plan(wl["coeffs"], wl["shape"], carry=operand, time_block=1)
+    p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=2, operand=operand)
+    y16, y32 = torch.empty_like(x16), torch.empty_like(x32)
+    p16.apply(x16, y16, 1)
+    p32.apply(x32, y32, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(y32.to(x16.dtype), y16)
+
+
+@pytest.mark.parametrize("name", ["1d3p_10240000", "1d5p_10240000"])
+def test_f32_carry_workload_tolerance_tiles_and_aliasing(oracle_mod, name):
+    import torch
+    wl = si.workload(name, small=True)
+    xd, x64 = to_dev(wl["make_grid"](np.float32), "f32")
+    ref = oracle_mod.apply(wl["coeffs"], x64, wl["steps"])
+    res = []
+    for th in (0, 1, 3, 17, 1000):
+        plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, tile_h=th)
+        res.append(run(plan, xd, wl["steps"]))
+    for r_ in res[1:]:
+        assert np.array_equal(r_, res[0])
+    rms, mx = rel_errors(res[0], ref)
+    print("%s f32 carry, split 3: rel-RMS %.3e rel-max %.3e" % (name, rms, mx))
+    assert rms <= 5e-5 and mx <= 5e-5
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3)
+    keep = xd.clone()
+    for steps in (0, 1, 2, 3):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), run(plan, xd, steps)), steps
+    assert torch.equal(xd, keep)

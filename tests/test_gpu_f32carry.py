@@ -138,20 +138,38 @@ def test_tile_heights_and_aliasing(oracle_mod):
     assert torch.equal(xd, keep)
 
 
-def test_batch_and_server_reject_f32_carry():
+def test_batch_and_server_accept_f32_carry(oracle_mod):
+    # fp32-carry plans (2-D and 3-D) run their own time loops inside a batch and inside
+    # the server's rounds: each result equals spider_apply of the same plan bit for bit,
+    # also when mixed with 16-bit grids
+    import time
     import torch
-    w = np.ones((3, 3)) / 9
-    plan = sp.Plan(w, (64, 64), carry="f32", engine="sparse", split=3)
-    x = torch.zeros((64, 64), dtype=torch.float32, device="cuda:0")
-    y = torch.empty_like(x)
-    with pytest.raises(sp.SpiderError) as e:
-        sp.apply_batch([plan], [x], [y], [2])
-    assert e.value.status == 2
+    cases = []
+    for name in ("box2d49p_10240", "box3d27p_512"):
+        wl = si.workload(name, small=True)
+        xd, _ = to_dev(wl["make_grid"](np.float32), "f32")
+        cases.append((sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3), xd, wl["steps"]))
+    wl = si.workload("star2d13p_8192", small=True)
+    x16, _ = to_dev(wl["make_grid"](), "f16")
+    cases.append((sp.Plan(wl["coeffs"], wl["shape"], carry="f16"), x16, 7))
+    want = [run(p, x, st) for p, x, st in cases]
+    outs = [torch.empty_like(x) for _, x, _ in cases]
+    sp.apply_batch([c[0] for c in cases], [c[1] for c in cases], outs, [c[2] for c in cases])
+    for o, w_ in zip(outs, want):
+        assert np.array_equal(from_dev(o), w_)
     srv = sp.Server(1 << 30)
-    with pytest.raises(sp.SpiderError) as e:
-        srv.submit(plan, x, y, 2)
-    assert e.value.status == 2
-    srv.close()
+    try:
+        outs = [torch.empty_like(x) for _, x, _ in cases]
+        tickets = [srv.submit(p, x, o, st) for (p, x, st), o in zip(cases, outs)]
+        t0 = time.time()
+        while not all(srv.poll(t)[0] for t in tickets):
+            assert time.time() - t0 < 60
+            time.sleep(0.001)
+        assert all(srv.poll(t)[1] == 0 for t in tickets)
+        for o, w_ in zip(outs, want):
+            assert np.array_equal(from_dev(o), w_)
+    finally:
+        srv.close()
 
 
 @pytest.mark.parametrize("operand", ["f16", "bf16"])

@@ -363,7 +363,7 @@ def test_invalid_arguments_rejected_without_gpu():
     assert "16-bit" in L.spider_last_error().decode()
     w3 = np.ones((3, 3, 3)) / 27
     shp3 = (ctypes.c_int64 * 3)(16, 16, 16)
-    o = opts(carry=1, engine=1, split=3)  # fp32 carry on the matrix engines: 2-D only
+    o = opts(carry=0, engine=1)  # no matrix engine takes an fp64 carry
     assert L.spider_plan(w3.ctypes.data, 3, shp3, 1, ctypes.byref(o), ctypes.byref(h)) == 2
     o = opts(carry=2, engine=1, split=3)  # the input split needs an fp32 carry
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
