@@ -161,6 +161,25 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
  */
 spider_status spider_apply(spider_plan_t plan, const void* in, void* out, int steps, void* stream);
 
+/*
+ * spider_apply_noalloc: spider_apply without any device memory allocation, for
+ * callers that cannot allocate (code under hipGraph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).
+ *   Same arguments, semantics and results (bit for bit) as spider_apply, but the
+ *   intermediate steps ping-pong through a fixed device array of
+ *   SPIDER_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it
+ *   runs on until the process ends, instead of the plan's own scratch buffer, and
+ *   the loop's launches are enqueued directly (no graph is built).  The first
+ *   call on a device looks the array's address up once (hipGetSymbolAddress).
+ *   Every call on one GPU shares that GPU's array: calls that overlap in time on
+ *   one GPU (from any plan, stream or thread) race and must not be issued.
+ *   Nothing in the array needs clearing between calls.
+ * Errors: INVALID (as spider_apply, and a grid larger than
+ * SPIDER_NOALLOC_SCRATCH_BYTES), HIP (launch failure).
+ */
+#define SPIDER_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+spider_status spider_apply_noalloc(spider_plan_t plan, const void* in, void* out, int steps, void* stream);
+
 /* Release the plan's device memory and cached graphs.  NULL is accepted. */
 spider_status spider_plan_destroy(spider_plan_t plan);
 

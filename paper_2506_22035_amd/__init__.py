@@ -52,6 +52,7 @@ def lib():
             "spider_opts_default": [P],
             "spider_plan": [P, I, P, I, P, P],
             "spider_apply": [P, P, P, I, P],
+            "spider_apply_noalloc": [P, P, P, I, P],
             "spider_plan_destroy": [P],
             "spider_plan_info": [P, P, P, P, P, P, P, P, P],
             "spider_plan_work": [P, I, P, P],
@@ -237,6 +238,14 @@ class Plan:
         self.check_tensor(x_out)
         _check(lib().spider_apply(self.handle, ctypes.c_void_p(x_in.data_ptr()), ctypes.c_void_p(x_out.data_ptr()),
                                   int(steps), _stream_handle(stream)))
+
+    def apply_noalloc(self, x_in, x_out, steps, stream=None):
+        """As apply, through the library's fixed device scratch array: allocates no device
+        memory (grids up to SPIDER_NOALLOC_SCRATCH_BYTES; calls on one GPU must not overlap)."""
+        self.check_tensor(x_in)
+        self.check_tensor(x_out)
+        _check(lib().spider_apply_noalloc(self.handle, ctypes.c_void_p(x_in.data_ptr()),
+                                          ctypes.c_void_p(x_out.data_ptr()), int(steps), _stream_handle(stream)))
 
     def close(self):
         if getattr(self, "_h", None) is not None:
