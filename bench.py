@@ -114,31 +114,46 @@ def load_oracle():
     return oracle
 
 
-def roofline(torch, sp, plan, xd, elem, npts, grid, operand, stream, headline_traffic):
-    """Roofline position of the plan's dominant kernel (its fused launch), timed over a
-    sustained loop of at least SUSTAIN_S seconds of fused launches only (HIP events on
-    `stream`).  Two roofs bound a launch from below: HBM (bytes moved / 8 TB/s) and the
-    matrix pipe (matrix instructions x 8192 multiply-adds x 2 / 2.5 PFLOP/s); the larger
+def roofline(torch, sp, plan, xd, elem, npts, grid, operand, stream, headline_traffic, steps, pass_ms):
+    """Sustained throughput and the roofline position of the plan's dominant kernel.
+
+    Sustained: passes of the workload (`steps` time steps from the same input, as in
+    the timed region) for at least SUSTAIN_S seconds.  Roofline: passes of only the
+    fused launches (the largest multiple of the fused depth not above `steps`), again
+    from the same input -- a long loop of one time loop would smooth the field, and
+    smoother data draws less power and runs at higher clocks -- for at least
+    SUSTAIN_S / 2 seconds; the launch time is their average (HIP events on `stream`).
+    Two roofs bound a launch from below: HBM (bytes moved / 8 TB/s) and the matrix
+    pipe (matrix instructions x 8192 multiply-adds x 2 / 2.5 PFLOP/s); the larger
     fraction is the binding one."""
     info = plan.info()
     tb = max(1, info["time_block"])
     yl = torch.empty_like(xd)
-    plan.apply(xd, yl, 4 * tb, stream=stream)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_s = max(20, int(math.ceil(SUSTAIN_S * 1e3 / max(pass_ms, 1e-3))))
+    plan.apply(xd, yl, steps, stream=stream)
+    torch.cuda.synchronize()
     e0.record(stream)
-    plan.apply(xd, yl, 20 * tb, stream=stream)
+    for _ in range(n_s):
+        plan.apply(xd, yl, steps, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    est = e0.elapsed_time(e1) / 20.0
-    n_l = max(20, int(math.ceil(SUSTAIN_S * 1e3 / max(est, 1e-3))))
+    ms_s = e0.elapsed_time(e1)
+    sustained = {"value": round(gstencil(npts, steps * n_s, ms_s), 2), "seconds": round(ms_s * 1e-3, 3),
+                 "passes": n_s, "ms_per_step": round(ms_s / n_s, 4),
+                 "method": "passes of the workload from the same input, back to back"}
+    nl = max(1, steps // tb)              # fused launches per roofline pass
+    n_r = max(20, int(math.ceil(0.5 * SUSTAIN_S * 1e3 / max(pass_ms * nl * tb / steps, 1e-3))))
+    plan.apply(xd, yl, nl * tb, stream=stream)
+    torch.cuda.synchronize()
     e0.record(stream)
-    plan.apply(xd, yl, n_l * tb, stream=stream)
+    for _ in range(n_r):
+        plan.apply(xd, yl, nl * tb, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     del yl
-    avg_s = ms * 1e-3 / n_l
+    avg_s = ms * 1e-3 / (n_r * nl)
     compulsory = npts * 2 * elem          # one read and one write of the state per launch
     charged = compulsory * tb             # the same per time step, all steps of the launch
     traffic = headline_traffic(tb, info["tile_h2"], grid)
@@ -169,11 +184,10 @@ def roofline(torch, sp, plan, xd, elem, npts, grid, operand, stream, headline_tr
                         "macs_per_instruction": MACS_PER_INSTRUCTION, "TFLOPs": round(mfma_tflops, 1),
                         "frac": round(mfma_frac, 4)}
     roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "time_steps_per_launch": tb,
-                 "launch_timing": "%d fused launches back to back (%.0f ms), after the timed passes" % (n_l, ms),
+                 "launch_timing": "%d passes of %d fused launches from the workload's input (%.0f ms), after the "
+                                  "timed passes" % (n_r, nl, ms),
                  "alg_GBs_charged": round(charged / avg_s / 1e9, 1),
                  "alg_bytes_charged_per_launch": charged})
-    sustained = {"value": round(gstencil(npts, n_l * tb, ms), 2), "seconds": round(ms * 1e-3, 3),
-                 "time_steps": n_l * tb, "launches": n_l}
     return roof, sustained
 
 
@@ -394,7 +408,8 @@ def size_trend(torch, sp, si, args):
         for band in (8, 16):
             p = sp.Plan(wl["coeffs"], (n, n), carry="f16", autotune=True, band_height=band)
             p.apply(x, y, 50)
-            k = max(3, min(50, int(4e9 / (n * n * 50))))
+            ms1, _ = timed_applies(torch, p, x, y, 50, 2, torch.cuda.current_stream())
+            k = max(5, int(math.ceil(250.0 / max(ms1 / 2, 1e-3))))   # about a quarter second of passes
             ms, _ = timed_applies(torch, p, x, y, 50, k, torch.cuda.current_stream())
             row["band%d_GStencil_s" % band] = round(n * n * 50 * k / (ms * 1e-3) / 1e9, 1)
             row["band%d_time_steps_per_launch" % band] = p.info()["time_block"]
@@ -588,7 +603,8 @@ def main():
             return measured_traffic(tb, tile_h2, grid)
         return None
 
-    roof, sustained = roofline(torch, sp, plan, xd, elem, npts, shape, operand, stream, traffic_lookup)
+    roof, sustained = roofline(torch, sp, plan, xd, elem, npts, shape, operand, stream, traffic_lookup, T,
+                               ms_per_step)
     roof["kernel"] = kernel_name(info, shape, args.carry, args.engine, rr, args.row_swap)
 
     # a plain device copy of the same grid: read + write of the same bytes, for reference
