@@ -80,6 +80,8 @@ typedef struct {
                        points, else two; other 2-D grids of radius <= 3 on the matrix
                        engines with a 16-bit carry or with paired-line bands: two; else
                        one; the dense engine fuses at most three),
+                       3-D grids: one (two fused steps, radius 1 with a 16-bit carry, only
+                       when asked for: measured slower on the 512^3 and 256^3 workloads),
                        1 = one step per launch, 2 = two where supported, 3 or 4 = that many
                        for paired-line bands with a 16-bit carry and for 1-D lines with
                        a 16-bit carry and radius <= 3 (else two where supported, else

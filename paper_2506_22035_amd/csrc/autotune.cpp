@@ -166,7 +166,8 @@ static hipError_t tune_fused(spider_plan_s* p, void* tmp, hipStream_t s, hipEven
   hipError_t e = hipSuccess;
   int best = *h;
   float best_ms = 1e30f;
-  const std::vector<int> cand = candidates(*h, p->ndim == 1 ? p->grid_tb2.nstrips : p->ny);
+  const std::vector<int> cand =
+      candidates(*h, p->ndim == 1 ? p->grid_tb2.nstrips : p->ndim == 3 ? p->nz : p->ny);
   for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
     set_tile2(p, cand[i]);
     if (launch_step2(p, p->d_scratch, tmp, s) != SPIDER_OK) return hipErrorUnknown;  // warm-up

@@ -106,6 +106,12 @@ hipError_t launch_band1d_tbt(int r, int operand, int engine, int T, const BandGr
 // Resident 64-lane workgroups per CU of the 2-D band kernel (0 on error).
 int band2d_blocks_per_cu(int r, int operand, int engine, bool aligned);
 int band3d_blocks_per_cu(int r, int operand, int engine, bool aligned, uint32_t rowmask);
+// Two fused steps of the 3-D band engine (radius 1, 16-bit carry): workgroups of two
+// waves (one per step); strip s computes x in [240 s - 8, 240 s + 248) and stores
+// [240 s, 240 s + 240) (nstrips = ceil(nx / 240)); nsegs_y = ceil(ny / kRowsY3),
+// seg_h planes per workgroup.  Resident two-wave workgroups per CU for sizing.
+hipError_t launch_band3d_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s);
+int band3d_tb2_blocks_per_cu(int r, int operand, int engine, uint32_t rowmask);
 
 // ------------------------------------------------------------------ batched launch
 // Body selected per grid inside the batch kernel.

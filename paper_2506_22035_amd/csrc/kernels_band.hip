@@ -664,6 +664,16 @@ hipError_t launch_band2d_xswap(int r, int operand, const BandGrid& g, hipStream_
 }
 
 // ----------------------------------------------------------------------------- 3-D
+// LDS ordering across the waves of a workgroup: this wave's LDS operations are
+// complete, then every wave reaches the barrier (global loads and stores stay in
+// flight, unlike __syncthreads()).
+__device__ __forceinline__ void lds_barrier3() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt and expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Kernel row (dz, dy) is packed as row dz * (2r+1) + dy.  MASK has bit
 // dz * (2r+1) + dy set for the rows that are multiplied (compile time, so star
 // shapes skip their all-zero rows without branches).
@@ -817,6 +827,229 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((ENG == 1 &&
   band3d_body<R, OP, ENG, ALIGNED, MASK>(g, w, lds);
 }
 
+// ----------------------------------------------------------------------------- 3-D, two fused steps
+// Two time steps per launch (radius 1, 16-bit carry).  A workgroup of two waves
+// owns a strip of 256 computed columns starting at x0 = 240 s - 8 (chunks at
+// x = 8 mod 16), kRowsY3 output lines and a segment of planes, and stores the
+// 240 columns [x0 + 8, x0 + 248) whose intermediate neighbourhood lies inside the
+// strip.  Wave 0 streams input planes (z0 - 2 ..) and accumulates the
+// intermediate step on kRowsY3 + 2 lines (yb0 - 1 ..) in 2r + 1 rotating plane
+// accumulators; each finished intermediate plane is rounded to the carry type,
+// zeroed outside the grid (the zero halo of the second step) and written to a
+// two-slot LDS ring.  Wave 1 streams those planes one iteration later into its
+// own rotating accumulators and stores the output planes.  One workgroup barrier
+// per plane orders each ring write before its read and the read before the slot
+// is written again.
+constexpr int kStripW3Fused = 240;
+
+template <int R, int OP, int ENG, bool ALIGNED, uint32_t MASK, bool ROLE1>
+__device__ __forceinline__ void band3d_tb2_wave(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int NR = RR * RR;
+  constexpr int YB = kRowsY3;
+  constexpr int YI = YB + 2 * R;      // intermediate lines per plane
+  constexpr int NLY = YI + 2 * R;     // input lines per plane
+  const int lane = threadIdx.x & 63;
+  int t = w;
+  const int strip = t % g.nstrips;
+  t /= g.nstrips;
+  const int sy = t % g.nsegs_y, sz = t / g.nsegs_y;
+  const int x0 = strip * kStripW3Fused - 8, yb0 = sy * YB, z0 = sz * g.seg_h;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int hz = min(g.seg_h, nz - z0);
+  // input planes z0 - 2R + pj; wave 1's output plane pj - 5 R (R = 1) is complete at pj
+  const int npl = ((hz + 5 * R + RR - 1) / RR) * RR;
+
+  u32x4 A[NR], Dh[NR], Dl[NR];
+  uint32_t I[(NR + 1) / 2];
+#pragma unroll
+  for (int a = 0; a < NR; ++a) {
+    if constexpr (ENG == 1) {
+      A[a] = (MASK >> a & 1u) ? reinterpret_cast<const u32x4*>(g.apack)[a * 64 + lane] : (u32x4){0, 0, 0, 0};
+      Dh[a] = Dl[a] = (u32x4){0, 0, 0, 0};
+    } else {
+      A[a] = (u32x4){0, 0, 0, 0};
+      Dh[a] = (MASK >> a & 1u) ? reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 0] : (u32x4){0, 0, 0, 0};
+      Dl[a] = (MASK >> a & 1u) ? reinterpret_cast<const u32x4*>(g.dpack)[(a * 64 + lane) * 2 + 1] : (u32x4){0, 0, 0, 0};
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < (NR + 1) / 2; ++a) I[a] = (ENG == 1) ? g.ipack[a * 64 + lane] : 0u;
+
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const int lb = nx * 2;
+  const int64_t pbytes = (int64_t)ny * lb;
+  uint32_t* ring = lds + NLY * kLdsRowDw + kLdsSpareDw;  // 2 slots x YI lines
+  // this lane's 4 values of a line: x = x0 + 16 n + 4 h + e
+  const int xl = x0 + 16 * (lane & 15) + 4 * (lane >> 4);
+  const int rw = lds_phys(8 * (lane & 15) + 2 * (lane >> 4) + 4);  // their dwords in a staged row
+
+  f32x4 acc[RR][ROLE1 ? YB : YI];
+#pragma unroll
+  for (int s2 = 0; s2 < RR; ++s2)
+#pragma unroll
+    for (int b = 0; b < (ROLE1 ? YB : YI); ++b) acc[s2][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  if constexpr (!ROLE1) {
+    // ---------------------------------------------------------------- wave 0: input -> intermediate
+    const uint32_t lvoff = chunk_voffset(x0, lane);
+    const int lw = chunk_lds_offset(lane, NLY * kLdsRowDw);
+    const int lstride = lane < kRowChunks ? kLdsRowDw : 0;
+    uint64_t in_addr = reinterpret_cast<uint64_t>(g.in) + ((int64_t)(z0 - 2 * R) * ny + (yb0 - 2 * R)) * lb;
+    int zin = z0 - 2 * R;
+    u32x4 stg[NLY];
+    auto stage = [&]() {
+      const bool zv = (unsigned)zin < (unsigned)nz;
+#pragma unroll
+      for (int l = 0; l < NLY; ++l) {
+        const bool valid = zv && (unsigned)(yb0 - 2 * R + l) < (unsigned)ny;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void*>(in_addr + (uint64_t)(l * lb)), (short)0, valid ? lb : 0, kRsrcWord3);
+        stg[l] = load_chunk<ALIGNED>(rs, lvoff);
+      }
+      in_addr += (uint64_t)pbytes;
+      ++zin;
+    };
+    // 16-bit lanes of the intermediate values inside the grid (columns)
+    uint32_t m0 = 0, m1 = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (xl + e >= 0 && xl + e < nx) (e < 2 ? m0 : m1) |= (e & 1) ? 0xffff0000u : 0x0000ffffu;
+    stage();
+    __builtin_amdgcn_s_waitcnt(0);
+    lds_barrier3();  // the ring is zeroed
+    for (int pb = 0; pb < npl; pb += RR) {
+#pragma unroll
+      for (int q = 0; q < RR; ++q) {
+        const int pj = pb + q;
+        if (lane < kRowChunks) {
+#pragma unroll
+          for (int l = 0; l < NLY; ++l) store_chunk_lds(lds, lw + l * lstride, stg[l]);
+        }
+        stage();  // plane pj + 1
+        wave_lds_sync();
+#pragma unroll
+        for (int l = 0; l < NLY; ++l) {
+          const uint32_t* lrow = lds + l * kLdsRowDw;
+          const u32x4 bv = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+#pragma unroll
+          for (int dz = 0; dz < RR; ++dz) {
+            const int slot = ((q - dz) % RR + RR) % RR;
+#pragma unroll
+            for (int b = 0; b < YI; ++b) {
+              const int dy = l - b;  // input line yb0 - 2R + l feeds intermediate line yb0 - R + b
+              if (dy < 0 || dy >= RR) continue;
+              const int a = dz * RR + dy;
+              if (!(MASK >> a & 1u)) continue;
+              if (a & 1)
+                acc[slot][b] = band_mma<OP, ENG, 1>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bv);
+              else
+                acc[slot][b] = band_mma<OP, ENG, 0>(acc[slot][b], A[a], Dh[a], Dl[a], I[a / 2], bv);
+            }
+          }
+        }
+        // intermediate plane z0 - R + (pj - 2R) is complete: round, zero outside the grid
+        const int fs = (q + 1) % RR;
+        const int zi = z0 - R + pj - 2 * R;
+        uint32_t* slotp = ring + (pj & 1) * YI * kLdsRowDw;
+#pragma unroll
+        for (int b = 0; b < YI; ++b) {
+          const uint2 v = pack_out<OP>(acc[fs][b]);
+          const bool ok = (unsigned)zi < (unsigned)nz && (unsigned)(yb0 - R + b) < (unsigned)ny;
+          *reinterpret_cast<uint2*>(slotp + b * kLdsRowDw + rw) = make_uint2(ok ? (v.x & m0) : 0u, ok ? (v.y & m1) : 0u);
+          acc[fs][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+        lds_barrier3();
+      }
+    }
+  } else {
+    // ---------------------------------------------------------------- wave 1: intermediate -> output
+    uint32_t ov[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int x = xl + (ALIGNED ? 0 : e);
+      ov[e] = (x >= x0 + 8 && x < x0 + 8 + kStripW3Fused && x < nx) ? (uint32_t)(x * 2) : kOffNone;
+    }
+    uint64_t out_addr = reinterpret_cast<uint64_t>(g.out) + ((int64_t)z0 * ny + yb0) * lb;
+    auto store_plane = [&](int k, const uint2* vals) {
+#pragma unroll
+      for (int b = 0; b < YB; ++b) {
+        const bool okp = k >= 0 && k < hz && yb0 + b < ny;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void*>(out_addr + (uint64_t)(b * lb)), (short)0, okp ? lb : 0, kRsrcWord3);
+        if constexpr (ALIGNED) {
+          typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+          __builtin_amdgcn_raw_buffer_store_b64((u32x2){vals[b].x, vals[b].y}, rs, ov[0], 0, kStoreNT);
+        } else {
+          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(vals[b].x & 0xffff), rs, ov[0], 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(vals[b].x >> 16), rs, ov[1], 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(vals[b].y & 0xffff), rs, ov[2], 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(vals[b].y >> 16), rs, ov[3], 0, 0);
+        }
+      }
+      if (k >= 0) out_addr += (uint64_t)pbytes;
+    };
+    uint2 done[YB];
+    int done_plane = -1000;
+    __builtin_amdgcn_s_waitcnt(0);
+    lds_barrier3();
+    for (int pb = 0; pb < npl; pb += RR) {
+#pragma unroll
+      for (int q = 0; q < RR; ++q) {
+        const int pj = pb + q;
+        // the intermediate plane wave 0 finished at pj - 1: plane index m = pj - 1 - 2R
+        // (z = z0 - R + m); it feeds output planes m - dz (z = z0 + m - dz)
+        const uint32_t* slotp = ring + ((pj + 1) & 1) * YI * kLdsRowDw;
+        if (done_plane > -1000) store_plane(done_plane, done);
+#pragma unroll
+        for (int b = 0; b < YI; ++b) {
+          const uint32_t* lrow = slotp + b * kLdsRowDw;
+          const u32x4 bv = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+#pragma unroll
+          for (int dz = 0; dz < RR; ++dz) {
+            const int slot = ((q - dz) % RR + RR) % RR;
+#pragma unroll
+            for (int o = 0; o < YB; ++o) {
+              const int dy = b - o;  // intermediate line yb0 - R + b feeds output line yb0 + o
+              if (dy < 0 || dy >= RR) continue;
+              const int a = dz * RR + dy;
+              if (!(MASK >> a & 1u)) continue;
+              if (a & 1)
+                acc[slot][o] = band_mma<OP, ENG, 1>(acc[slot][o], A[a], Dh[a], Dl[a], I[a / 2], bv);
+              else
+                acc[slot][o] = band_mma<OP, ENG, 0>(acc[slot][o], A[a], Dh[a], Dl[a], I[a / 2], bv);
+            }
+          }
+        }
+        // output plane k = m - 2R = pj - 1 - 4R (z = z0 + k) is complete
+        const int fs = (q + 1) % RR;
+#pragma unroll
+        for (int o = 0; o < YB; ++o) {
+          done[o] = pack_out<OP>(acc[fs][o]);
+          acc[fs][o] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+        done_plane = pj - 1 - 4 * R;
+        lds_barrier3();
+      }
+    }
+    if (done_plane > -1000) store_plane(done_plane, done);
+  }
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, uint32_t MASK>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu((ENG == 2 && !ALIGNED) ? 1 : 2))) void band3d_tb2_kernel(BandGrid g) {
+  constexpr int YI = kRowsY3 + 2 * R;
+  constexpr int NLY = YI + 2 * R;
+  __shared__ uint32_t lds[NLY * kLdsRowDw + kLdsSpareDw + 2 * YI * kLdsRowDw];
+  for (int i = threadIdx.x; i < 2 * YI * kLdsRowDw; i += 128) lds[NLY * kLdsRowDw + kLdsSpareDw + i] = 0u;
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0)
+    band3d_tb2_wave<R, OP, ENG, ALIGNED, MASK, false>(g, w, lds);
+  else
+    band3d_tb2_wave<R, OP, ENG, ALIGNED, MASK, true>(g, w, lds);
+}
+
 template <int OP, int ENG, bool AL>
 static hipError_t dispatch3d(int r, const BandGrid& g, hipStream_t s) {
   const dim3 grid(g.nblocks), block(64);
@@ -826,6 +1059,46 @@ static hipError_t dispatch3d(int r, const BandGrid& g, hipStream_t s) {
   else
     hipLaunchKernelGGL((band3d_kernel<1, OP, ENG, AL, box_mask3<1>()>), grid, block, 0, s, g);
   return hipGetLastError();
+}
+
+template <int OP, int ENG, bool AL>
+static hipError_t dispatch3d_tb2(const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(128);
+  if ((g.rowmask & ~star_mask3<1>()) == 0)
+    hipLaunchKernelGGL((band3d_tb2_kernel<1, OP, ENG, AL, star_mask3<1>()>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((band3d_tb2_kernel<1, OP, ENG, AL, box_mask3<1>()>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_band3d_tb2(int r, int operand, int engine, const BandGrid& g, hipStream_t s) {
+  if (r != 1) return hipErrorInvalidValue;
+  const bool al = (g.nx % 8) == 0;
+  if (operand == 2 && engine == 1) return al ? dispatch3d_tb2<2, 1, true>(g, s) : dispatch3d_tb2<2, 1, false>(g, s);
+  if (operand == 2 && engine == 2) return al ? dispatch3d_tb2<2, 2, true>(g, s) : dispatch3d_tb2<2, 2, false>(g, s);
+  if (operand == 3 && engine == 1) return al ? dispatch3d_tb2<3, 1, true>(g, s) : dispatch3d_tb2<3, 1, false>(g, s);
+  if (operand == 3 && engine == 2) return al ? dispatch3d_tb2<3, 2, true>(g, s) : dispatch3d_tb2<3, 2, false>(g, s);
+  return hipErrorInvalidValue;
+}
+
+template <int OP, int ENG>
+static int occ3d_tb2(uint32_t rowmask) {
+  int nb = 0;
+  hipError_t e;
+  if ((rowmask & ~star_mask3<1>()) == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band3d_tb2_kernel<1, OP, ENG, true, star_mask3<1>()>, 128, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band3d_tb2_kernel<1, OP, ENG, true, box_mask3<1>()>, 128, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+int band3d_tb2_blocks_per_cu(int r, int operand, int engine, uint32_t rowmask) {
+  if (r != 1) return 0;
+  if (operand == 2 && engine == 1) return occ3d_tb2<2, 1>(rowmask);
+  if (operand == 2 && engine == 2) return occ3d_tb2<2, 2>(rowmask);
+  if (operand == 3 && engine == 1) return occ3d_tb2<3, 1>(rowmask);
+  if (operand == 3 && engine == 2) return occ3d_tb2<3, 2>(rowmask);
+  return 0;
 }
 
 hipError_t launch_band3d(int r, int operand, int engine, const BandGrid* /*grids_dev*/, const BandGrid* grids_host,

@@ -185,7 +185,8 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   g.in = src;
   g.out = dst;
   hipError_t e =
-      p->ndim == 1 ? launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+      p->ndim == 1   ? launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+      : p->ndim == 3 ? launch_band3d_tb2(p->r, p->operand, p->engine, g, s)
       : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
       : p->carry == SPIDER_F32
           ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, p->time_block, g, s)
@@ -237,6 +238,15 @@ void set_tile2(spider_plan_s* p, int h) {
     p->grid_tb2.nblocks = p->grid_tb2.nsegs_y;
     return;
   }
+  if (p->ndim == 3) {  // planes per two-wave workgroup
+    h = std::max(1, std::min(h, p->nz));
+    p->tile_h2 = h;
+    p->grid_tb2.seg_h = h;
+    p->grid_tb2.nsegs_y = (p->ny + kRowsY3 - 1) / kRowsY3;
+    p->grid_tb2.nsegs_z = (p->nz + h - 1) / h;
+    p->grid_tb2.nblocks = p->grid_tb2.nstrips * p->grid_tb2.nsegs_y * p->grid_tb2.nsegs_z;
+    return;
+  }
   if (p->band_h == 8) h += h & 1;  // paired-line bands: segments start on even rows
   p->tile_h2 = h;
   p->grid_tb2.seg_h = h;
@@ -258,6 +268,17 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
     const long long nblk = p->grid_template.nstrips;
     const long long h = (nblk + 12LL * ncu - 1) / (12LL * ncu);
     return (int)std::min<long long>(std::max<long long>(h, 16), nblk);
+  }
+  if (p->ndim == 3) {
+    // one resident round of two-wave workgroups over (strip, 4-line block, plane segment)
+    int per_cu3 = band3d_tb2_blocks_per_cu(p->r, p->operand, p->engine, p->rowmask);
+    if (per_cu3 <= 0) per_cu3 = 4;
+    const long long slots3 = (long long)ncu * per_cu3;
+    const long long cols = (long long)p->grid_tb2.nstrips * ((p->ny + kRowsY3 - 1) / kRowsY3);
+    const long long segs3 = std::max<long long>(1, slots3 / cols);
+    long long h3 = (p->nz + segs3 - 1) / segs3;
+    h3 = std::max<long long>(h3, 8);
+    return (int)std::min<long long>(h3, p->nz);
   }
   int per_cu = p->band_h != 8 ? band2d_tb2_blocks_per_cu(p->r, p->operand, p->engine)
                : p->carry == SPIDER_F32
@@ -654,7 +675,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     g.nblocks = ndim == 1 ? g.nsegs_y : g.nstrips * g.nsegs_y * g.nsegs_z;
     set_batch_geometry(p);
     // two fused steps per launch: 2-D, radius <= 3, a 16-bit carry or paired-line bands
-    const bool tb2_ok = ndim == 2 && radius <= 3 && (low || pair) && !p->row_swap;
+    const bool tb2_ok = (ndim == 2 && radius <= 3 && (low || pair) && !p->row_swap) ||
+                        (ndim == 3 && radius == 1 && low);
     // three or four: paired-line bands with a 16-bit carry (the dense engine
     // measured slower at four); three with an fp32 carry on the sparse engine
     const bool f32_tbt = pair && o.carry == SPIDER_F32 && engine == SPIDER_ENGINE_SPARSE;
@@ -666,7 +688,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     if (o.time_block == 0) {
       // deeper fusion pays on large grids; small ones lack waves to hide its longer pipeline
       const long long pts = (long long)p->ny * p->nx;
-      T = ndim == 1 ? (pts >= (1LL << 22) ? 4 : 2) : pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2;
+      // 3-D grids run one step per launch unless two are asked for (time_block = 2)
+      T = ndim == 3 ? 1 : ndim == 1 ? (pts >= (1LL << 22) ? 4 : 2) : pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2;
       p->tune_depth = o.autotune && o.tile_h == 0 && p->max_time_block > 2;
     } else {
       T = o.time_block;
