@@ -191,6 +191,24 @@ def roofline(torch, sp, plan, xd, elem, npts, grid, operand, stream, headline_tr
     return roof, sustained
 
 
+def matrix_ceiling(sp, engine, stream, waves=(2, 4), iterations=200000):
+    """Sustained fp16 matrix-instruction rates of this GPU (spider_measure_matrix_rate):
+    the sparse and the dense instruction at each residency in `waves` (waves per SIMD),
+    with the clock the chip holds.  The fused kernels hold two waves per SIMD."""
+    out = {}
+    for kind in ("sparse", "dense"):
+        for w in waves:
+            m = sp.measure_matrix_rate(kind == "sparse", w, iterations, stream=stream)
+            out["%s_w%d" % (kind, w)] = {"TFLOPs": round(m["TFLOPs"], 1), "clock_GHz": round(m["clock_GHz"], 3),
+                                         "cycles_per_instruction": round(m["cycles_per_instruction"], 2)}
+    out["sparse_over_dense"] = {"w%d" % w: round(out["sparse_w%d" % w]["TFLOPs"] / out["dense_w%d" % w]["TFLOPs"], 3)
+                                for w in waves}
+    out["method"] = ("register-resident fp16 operands, 8 independent accumulators per wave, %d x 8 instructions "
+                     "per wave after a warm-up launch; TFLOP/s counts 2 x 16 x 16 x 32 flop per instruction"
+                     % iterations)
+    return out
+
+
 def kernel_name(info, shape, carry, engine, r, row_swap):
     tb = info["time_block"]
     if engine == "direct":
@@ -606,6 +624,16 @@ def main():
     roof, sustained = roofline(torch, sp, plan, xd, elem, npts, shape, operand, stream, traffic_lookup, T,
                                ms_per_step)
     roof["kernel"] = kernel_name(info, shape, args.carry, args.engine, rr, args.row_swap)
+    ceiling = None
+    if "mfma" in roof and not args.no_extras:
+        # the matrix pipe's attainable rate at the fused kernel's residency (two waves per
+        # SIMD), beside the published peak: power holds the clock below its 2.4 GHz boost
+        ceiling = matrix_ceiling(sp, info["engine"], stream)
+        att = ceiling["%s_w2" % ("dense" if info["engine"] == "dense" else "sparse")]
+        roof["mfma"]["attainable_TFLOPs"] = att["TFLOPs"]
+        roof["mfma"]["attainable_source"] = ("spider_measure_matrix_rate, %s fp16, 2 waves per SIMD "
+                                             "(the fused kernel's residency)" % info["engine"])
+        roof["mfma"]["frac_of_attainable"] = round(roof["mfma"]["TFLOPs"] / att["TFLOPs"], 4)
 
     # a plain device copy of the same grid: read + write of the same bytes, for reference
     z = torch.empty_like(xd)
@@ -639,6 +667,8 @@ def main():
            "launches_per_step": launches,
            "matrix_instructions_per_step": mi_pass,
            "roofline": roof}
+    if ceiling is not None:
+        out["matrix_rate"] = ceiling
 
     if not args.no_extras:
         oracle = load_oracle()

@@ -215,6 +215,29 @@ spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int*
 spider_status spider_plan_work(spider_plan_t plan, int steps, uint64_t* launches, uint64_t* matrix_instructions);
 
 /*
+ * spider_measure_matrix_rate: the rate at which the current device sustains fp16
+ * matrix instructions with register-resident operands and no memory traffic:
+ * 2:4-sparse smfmac 16x16x64 (sparse = 1) or dense mfma 16x16x32 (sparse = 0).
+ * Both do 16 x 16 x 32 multiply-adds per instruction; the sparse unit selects 2
+ * of every 4 inputs first (Sec. 2.1), so the ratio of the two rates is the
+ * speedup the sparse engine can bring here, and the sparse rate is the matrix
+ * ceiling the stencil kernels run against at the same occupancy.
+ *   waves_per_simd          1..4 resident waves per SIMD (one-wave workgroups)
+ *   iterations              1..10^7; each wave issues 8 x iterations instructions
+ *   stream                  hipStream_t as void* (NULL = default stream)
+ *   dense_equiv_tflops      out: 2 x 16 x 16 x 32 flop per instruction / second
+ *   clock_ghz               out (may be NULL): shader clock held meanwhile,
+ *                           from the shader-cycle and 100 MHz real-time counters
+ *   cycles_per_instruction  out (may be NULL): clock cycles per instruction per SIMD
+ * Synchronous: allocates two small device buffers, runs a warm-up launch and a
+ * timed one, frees the buffers.  Measurement only; no stencil state is touched.
+ * Errors: INVALID (arguments out of range, null dense_equiv_tflops), OOM, HIP.
+ */
+spider_status spider_measure_matrix_rate(int sparse, int waves_per_simd, int iterations, void* stream,
+                                         double* dense_equiv_tflops, double* clock_ghz,
+                                         double* cycles_per_instruction);
+
+/*
  * Batched apply (launches over the tiles of every grid).
  * Runs grids of uneven size and stencil shape together.  Launch k advances
  * every grid that still has work: 2-D grids with paired-line bands by two fused

@@ -56,6 +56,7 @@ def lib():
             "spider_plan_destroy": [P],
             "spider_plan_info": [P, P, P, P, P, P, P, P, P],
             "spider_plan_work": [P, I, P, P],
+            "spider_measure_matrix_rate": [I, I, I, P, P, P, P],
             "spider_apply_batch": [I, P, P, P, P, P],
             "spider_server_create": [ctypes.c_size_t, I, I, P],
             "spider_submit": [P, P, P, P, I, P],
@@ -91,6 +92,16 @@ def version():
 
 def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data)
+
+
+def measure_matrix_rate(sparse=True, waves_per_simd=2, iterations=20000, stream=None):
+    """Sustained fp16 matrix-instruction rate of the current device (spider.h):
+    dict with dense-equivalent TFLOP/s, the shader clock held meanwhile (GHz) and
+    clock cycles per instruction per SIMD."""
+    t, g, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().spider_measure_matrix_rate(1 if sparse else 0, int(waves_per_simd), int(iterations), stream,
+                                            ctypes.byref(t), ctypes.byref(g), ctypes.byref(c)))
+    return {"TFLOPs": t.value, "clock_GHz": g.value, "cycles_per_instruction": c.value}
 
 
 # ------------------------------------------------------------------ planner introspection (host only)
