@@ -299,6 +299,153 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XLO ? 2 : 3)
   band1d_f32_body<R, OP, ENG, ALIGNED, XLO>(g, w, lds);
 }
 
+// T = 2..4 fp32-carry time steps per launch on the 1-D band engine.  The block
+// stream is that of the 16-bit fused 1-D kernel: level t of block k covers x in
+// [256 k - 8, 256 k + 248) and its staged row x in [256 k - 16, 256 k + 256);
+// at stream iteration i level t + 1 of block s0 + i - 2 t is computed from the
+// level-t rows, held in rings of four rows per intermediate level.  Here every
+// level is kept as its fp32 sums, split into a 16-bit hi (and lo) row exactly as
+// a single fp32-carry step splits its fp32 input after loading it, and zero
+// outside the line; so each output equals that of T single steps bit for bit,
+// while the grid crosses HBM once per launch instead of once per step.
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T>
+__device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int U = 4;             // input blocks staged per body (the ring size)
+  constexpr int NS = XLO ? 2 : 1;  // LDS rows per level of a block: hi (and lo)
+  constexpr int ROWDW = NS * kLdsRowDw;
+  const int lane = threadIdx.x;
+  const int b0 = w * g.seg_h;
+  const int nb = min(g.seg_h, g.nstrips - b0);
+  const int s0 = b0 - (T - 1);
+  const int nin = nb + 2 * (T - 1);  // input blocks level 1 needs
+  const int nit = nb + 3 * (T - 1);  // iterations until the last output block
+  const int nx = g.nx;
+  const u32x4 A0 = (ENG == 1) ? reinterpret_cast<const u32x4*>(g.apack)[lane] : (u32x4){0, 0, 0, 0};
+  const u32x4 Dh = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 0];
+  const u32x4 Dl = (ENG == 1) ? (u32x4){0, 0, 0, 0} : reinterpret_cast<const u32x4*>(g.dpack)[lane * 2 + 1];
+  const uint32_t I0 = (ENG == 1) ? g.ipack[lane] : 0u;
+  __builtin_amdgcn_s_waitcnt(0);
+  int p1, p2;
+  band_gather_offsets(lane, &p1, &p2);
+  const __amdgpu_buffer_rsrc_t rin =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * 4, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * 4, kRsrcWord3);
+  // staging: lane l writes row positions 4 l .. 4 l + 3, lanes 0..15 also position 256 + l
+  const int mw = lds_phys(2 * lane);
+  const int tw_line = lds_phys(128 + (lane >> 1)) * 4 + 2 * (lane & 1);
+  const int spare_tw = (U * ROWDW) * 4;
+  // this lane's 4 values of a block: x = 256 k + ox + e, row position 8 + 16 n + 4 h
+  const int n = lane & 15, h = lane >> 4;
+  const int ox = -8 + 16 * n + 4 * h;
+  const int wmain = lds_phys(4 + 8 * n + 2 * h);
+  const bool head = n == 0 && h < 2, tail = n == 15 && h >= 2;  // first / last 8 values of the block
+  const int whead = lds_phys(132 + 2 * h), wtail = lds_phys(2 * (h - 2));
+  uint32_t* ring = lds + U * ROWDW + 64;  // (T - 1) levels x 4 rows, after the staged rows and a spare area
+  for (int i = lane; i < (T - 1) * 4 * ROWDW; i += 64) ring[i] = 0u;
+
+  auto load_blk = [&](int it) {  // input block s0 + it, zero where level 1 does not need it
+    const int x0 = 256 * (s0 + it) - 8;
+    const bool v = it < nin;
+    const uint32_t mvoff = v ? (uint32_t)((x0 - 8 + 4 * lane) * 4) : kOffNone;
+    const uint32_t tvoff = (v && lane < 16) ? (uint32_t)((x0 + 248 + lane) * 4) : kOffNone;
+    return load_f32_line<ALIGNED>(rin, mvoff, tvoff);
+  };
+  auto out_off = [&](int it) {  // output block of iteration it
+    const int k = s0 + it - 2 * (T - 1);
+    const int x = 256 * k + ox;
+    return (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 4) : kOffNone;
+  };
+  F32Line stg[U];
+#pragma unroll
+  for (int q = 0; q < U; ++q) stg[q] = load_blk(q);
+  f32x4 done[U];
+  const int nbody = (nit + U - 1) / U;
+  for (int jb = 0; jb < nbody * U; jb += U) {
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      uint32_t* hl = lds + q * ROWDW;
+      const int tw = lane < 16 ? tw_line + q * ROWDW * 4 : spare_tw;
+      uint32_t h0, l0, h1, l1, th, tl;
+      split2<OP, XLO>(stg[q].m.x, stg[q].m.y, &h0, &l0);
+      split2<OP, XLO>(stg[q].m.z, stg[q].m.w, &h1, &l1);
+      split2<OP, XLO>(stg[q].t, 0u, &th, &tl);
+      *reinterpret_cast<uint2*>(hl + mw) = make_uint2(h0, h1);
+      *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + tw) = (uint16_t)th;
+      if constexpr (XLO) {
+        *reinterpret_cast<uint2*>(hl + kLdsRowDw + mw) = make_uint2(l0, l1);
+        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lds) + tw + (lane < 16 ? kLdsRowDw * 4 : 0)) =
+            (uint16_t)tl;
+      }
+    }
+    if (jb > 0) {
+#pragma unroll
+      for (int q = 0; q < U; ++q) store_f32x4<ALIGNED>(rout, out_off(jb - U + q), done[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) stg[q] = load_blk(jb + U + q);
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int it = jb + q;
+      wave_lds_sync();  // rows written by the previous iteration are visible
+      f32x4 acc[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        // level t + 1 of block s0 + it - 2t reads the level-t row (input row q for t = 0)
+        const uint32_t* row = (t == 0) ? lds + q * ROWDW : ring + ((t - 1) * 4 + ((q - 2 * t) & 3)) * ROWDW;
+        const u32x4 bh = {row[p1], row[p1 + 10], row[p2], row[p2 + 10]};
+        acc[t] = band_mma<OP, ENG, 0>((f32x4){0.f, 0.f, 0.f, 0.f}, A0, Dh, Dl, I0, bh);
+        if constexpr (XLO) {
+          const uint32_t* lrow = row + kLdsRowDw;
+          const u32x4 bl = {lrow[p1], lrow[p1 + 10], lrow[p2], lrow[p2 + 10]};
+          acc[t] = band_mma<OP, ENG, 0>(acc[t], A0, Dh, Dl, I0, bl);
+        }
+      }
+      done[q] = acc[T - 1];
+#pragma unroll
+      for (int t = 0; t + 1 < T; ++t) {
+        // level t + 1 of block k: zero outside the line, split, then into its row, the
+        // previous row's tail and the next row's head (ring slots by iteration)
+        // (the whole vector is cast first: element-wise casts of a float vector have been
+        // seen to compile to four copies of element 0)
+        const int x = 256 * (s0 + it - 2 * t) + ox;
+        u32x4 v = __builtin_bit_cast(u32x4, acc[t]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (x + e < 0 || x + e >= nx) v[e] = 0u;
+        uint32_t h0, l0, h1, l1;
+        split2<OP, XLO>(v.x, v.y, &h0, &l0);
+        split2<OP, XLO>(v.z, v.w, &h1, &l1);
+        uint32_t* lev = ring + t * 4 * ROWDW;
+        const int rho = q - 2 * t;
+        uint32_t* rm = lev + (rho & 3) * ROWDW;
+        *reinterpret_cast<uint2*>(rm + wmain) = make_uint2(h0, h1);
+        if constexpr (XLO) *reinterpret_cast<uint2*>(rm + kLdsRowDw + wmain) = make_uint2(l0, l1);
+        if (head) {
+          uint32_t* rh = lev + ((rho - 1) & 3) * ROWDW;
+          *reinterpret_cast<uint2*>(rh + whead) = make_uint2(h0, h1);
+          if constexpr (XLO) *reinterpret_cast<uint2*>(rh + kLdsRowDw + whead) = make_uint2(l0, l1);
+        }
+        if (tail) {
+          uint32_t* rt = lev + ((rho + 1) & 3) * ROWDW;
+          *reinterpret_cast<uint2*>(rt + wtail) = make_uint2(h0, h1);
+          if constexpr (XLO) *reinterpret_cast<uint2*>(rt + kLdsRowDw + wtail) = make_uint2(l0, l1);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < U; ++q) store_f32x4<ALIGNED>(rout, out_off(nbody * U - U + q), done[q]);
+}
+
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void band1d_f32_tbt_kernel(BandGrid g) {
+  constexpr int NS = XLO ? 2 : 1;
+  __shared__ uint32_t lds[4 * NS * kLdsRowDw + 64 + (T - 1) * 4 * NS * kLdsRowDw];
+  const int w = xcd_remap(blockIdx.x, gridDim.x);
+  band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T>(g, w, lds);
+}
+
 // ----------------------------------------------------------------------------- 3-D
 // The 3-D band engine (radius 1) with an fp32 carry: the decomposition of the
 // 16-bit 3-D kernel (a wave owns a 256-point strip, kRowsY3 output lines and a
@@ -580,6 +727,44 @@ hipError_t launch_band1d_f32(int r, int operand, int engine, bool xlo, const Ban
   if (operand == 2 && engine == 2) return dispatch1d_f32_al<2, 2>(r, xlo, g, s);
   if (operand == 3 && engine == 1) return dispatch1d_f32_al<3, 1>(r, xlo, g, s);
   if (operand == 3 && engine == 2) return dispatch1d_f32_al<3, 2>(r, xlo, g, s);
+  return hipErrorInvalidValue;
+}
+
+namespace {
+template <int OP, int ENG, bool AL, bool XLO, int T>
+hipError_t dispatch1d_f32_tbt(int r, const BandGrid& g, hipStream_t s) {
+  const dim3 grid(g.nblocks), block(64);
+  switch (r) {
+    case 1: hipLaunchKernelGGL((band1d_f32_tbt_kernel<1, OP, ENG, AL, XLO, T>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band1d_f32_tbt_kernel<2, OP, ENG, AL, XLO, T>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band1d_f32_tbt_kernel<3, OP, ENG, AL, XLO, T>), grid, block, 0, s, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template <int OP, int ENG, bool AL, bool XLO>
+hipError_t dispatch1d_f32_tbt_t(int r, int T, const BandGrid& g, hipStream_t s) {
+  if (T == 2) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 2>(r, g, s);
+  if (T == 3) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 3>(r, g, s);
+  if (T == 4) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 4>(r, g, s);
+  return hipErrorInvalidValue;
+}
+template <int OP, int ENG>
+hipError_t dispatch1d_f32_tbt_al(int r, bool xlo, int T, const BandGrid& g, hipStream_t s) {
+  const bool al = (g.nx % 4) == 0;
+  if (al)
+    return xlo ? dispatch1d_f32_tbt_t<OP, ENG, true, true>(r, T, g, s)
+               : dispatch1d_f32_tbt_t<OP, ENG, true, false>(r, T, g, s);
+  return xlo ? dispatch1d_f32_tbt_t<OP, ENG, false, true>(r, T, g, s)
+             : dispatch1d_f32_tbt_t<OP, ENG, false, false>(r, T, g, s);
+}
+}  // namespace
+
+hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s) {
+  if (operand == 2 && engine == 1) return dispatch1d_f32_tbt_al<2, 1>(r, xlo, T, g, s);
+  if (operand == 2 && engine == 2) return dispatch1d_f32_tbt_al<2, 2>(r, xlo, T, g, s);
+  if (operand == 3 && engine == 1) return dispatch1d_f32_tbt_al<3, 1>(r, xlo, T, g, s);
+  if (operand == 3 && engine == 2) return dispatch1d_f32_tbt_al<3, 2>(r, xlo, T, g, s);
   return hipErrorInvalidValue;
 }
 

@@ -185,7 +185,9 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   g.in = src;
   g.out = dst;
   hipError_t e =
-      p->ndim == 1   ? launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s)
+      p->ndim == 1   ? (p->carry == SPIDER_F32
+                            ? launch_band1d_f32_tbt(p->r, p->operand, p->engine, p->split == 3, p->time_block, g, s)
+                            : launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s))
       : p->ndim == 3 ? launch_band3d_tb2(p->r, p->operand, p->engine, g, s)
       : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
       : p->carry == SPIDER_F32
@@ -324,9 +326,11 @@ static spider_status launch_rem2(spider_plan_s* p, const void* src, void* dst, h
   BandGrid g = p->grid_rem2;
   g.in = src;
   g.out = dst;
-  // time_block > 2 exists for 1-D lines and for paired-line bands (16-bit carry, or
-  // fp32 carry on the sparse engine)
-  hipError_t e = p->ndim == 1             ? launch_band1d_tbt(p->r, p->operand, p->engine, 2, g, s)
+  // time_block > 2 exists for 1-D lines (16-bit or fp32 carry) and for paired-line
+  // bands (16-bit carry, or fp32 carry on the sparse engine)
+  hipError_t e = p->ndim == 1             ? (p->carry == SPIDER_F32
+                                                 ? launch_band1d_f32_tbt(p->r, p->operand, p->engine, p->split == 3, 2, g, s)
+                                                 : launch_band1d_tbt(p->r, p->operand, p->engine, 2, g, s))
                  : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, 2, g, s)
                                           : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -681,15 +685,18 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     // measured slower at four); three with an fp32 carry on the sparse engine
     const bool f32_tbt = pair && o.carry == SPIDER_F32 && engine == SPIDER_ENGINE_SPARSE;
     const bool tbt_ok = tb2_ok && pair && (low || f32_tbt);
-    // 1-D lines: two to four steps on the 16-point band engine (16-bit carry, r <= 3)
-    const bool tb1_ok = ndim == 1 && radius <= 3 && low && !p->row_swap;
+    // 1-D lines: two to four steps on the 16-point band engine (16-bit or fp32 carry, r <= 3)
+    const bool tb1_ok = ndim == 1 && radius <= 3 && (low || o.carry == SPIDER_F32) && !p->row_swap;
     p->max_time_block = tb1_ok ? 4 : !tb2_ok ? 1 : !tbt_ok ? 2 : (engine == SPIDER_ENGINE_DENSE || f32_tbt ? 3 : 4);
     int T;
     if (o.time_block == 0) {
       // deeper fusion pays on large grids; small ones lack waves to hide its longer pipeline
       const long long pts = (long long)p->ny * p->nx;
       // 3-D grids run one step per launch unless two are asked for (time_block = 2)
-      T = ndim == 3 ? 1 : ndim == 1 ? (pts >= (1LL << 22) ? 4 : 2) : pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2;
+      // 1-D lines with an fp32 carry: two (measured fastest on 10^7-point lines)
+      T = ndim == 3   ? 1
+          : ndim == 1 ? (o.carry == SPIDER_F32 ? 2 : pts >= (1LL << 22) ? 4 : 2)
+                      : (pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2);
       p->tune_depth = o.autotune && o.tile_h == 0 && p->max_time_block > 2;
     } else {
       T = o.time_block;

@@ -4,7 +4,9 @@ A fused launch sums every value exactly as a single step does, so it must equal
 single steps bit for bit on any data, and the oracle bit for bit on integer data
 whose every step stays below 2^11 (three taps of +-1, inputs in {-2..2}).  The
 cases cover lines shorter than a block, ragged ends, segments of one block, step
-counts that T does not divide and in-place applies.
+counts that T does not divide and in-place applies.  The fp32-carry fused kernel
+keeps every level as fp32 sums split into 16-bit hi (and lo) rows, exactly as a
+single fp32 step splits its input, so it too equals single steps bit for bit.
 """
 import numpy as np
 import pytest
@@ -79,6 +81,9 @@ def test_depth_limits():
     w4 = np.ones(9) / 9
     assert sp.Plan(w4, (4096,), carry="f16", time_block=4).info()["time_block"] == 1  # r > 3
     assert sp.Plan(w, (4096,), carry="f32", time_block=4).info()["time_block"] == 1  # direct engine
+    for eng in ("sparse", "dense"):
+        assert sp.Plan(w, (4096,), carry="f32", engine=eng, split=3, time_block=4).info()["time_block"] == 4
+        assert sp.Plan(w4, (4096,), carry="f32", engine=eng, split=3, time_block=4).info()["time_block"] == 1
 
 
 @pytest.mark.parametrize("T", [2, 3, 4])
@@ -87,4 +92,65 @@ def test_full_size_equals_single_steps(T):
     xd, _ = to_dev(wl["make_grid"](), "f16")
     a = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f16", time_block=T), xd, 12)
     b = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f16", time_block=1), xd, 12)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ fp32 carry
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+@pytest.mark.parametrize("engine,operand,split", [("sparse", "f16", 3), ("sparse", "bf16", 3), ("dense", "f16", 3),
+                                                  ("sparse", "f16", 2), ("dense", "bf16", 2)])
+def test_f32_fused_equals_single_steps(T, engine, operand, split):
+    wl = si.workload("1d5p_10240000", small=True)
+    for n in (7, 257, 4099, wl["shape"][0]):
+        x = wl["make_grid"](np.float32)[:n]
+        xd, _ = to_dev(x, "f32")
+        ref = run(sp.Plan(wl["coeffs"], (n,), carry="f32", engine=engine, operand=operand, split=split,
+                          time_block=1), xd, 11)
+        for th in (0, 1, 2, 5, 16, 1000):
+            plan = sp.Plan(wl["coeffs"], (n,), carry="f32", engine=engine, operand=operand, split=split,
+                           time_block=T, tile_h=th)
+            assert plan.info()["time_block"] == T
+            got = run(plan, xd, 11)
+            assert np.array_equal(got, ref), (n, th, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+@pytest.mark.parametrize("engine", ["sparse", "dense"])
+@pytest.mark.parametrize("n", LENGTHS)
+def test_f32_fused_integer_exact(oracle_mod, T, engine, n):
+    # all-ones taps (r = 1) on inputs in {1, 2} over nine steps: intermediate values
+    # pass 2^11 (exact only as hi + lo), outputs exact in fp32; and mixed-sign
+    # integer taps of radius 2 and 3
+    cases = [(np.ones(3), 9, (1, 2))] + [(sparse_int_taps_1d(r, 40 + r), 5, (-2, 2)) for r in (2, 3)]
+    for w, steps, (lo, hi) in cases:
+        xd, x64 = to_dev(si.grid_integer((n,), lo, hi, 7 + n % 89), "f32")
+        plan = sp.Plan(w, (n,), carry="f32", engine=engine, split=3, time_block=T)
+        assert plan.info()["time_block"] == T
+        ref = oracle_mod.apply(w, x64, steps)
+        assert np.abs(oracle_mod.apply(w, x64, steps - 1)).max() < 65504
+        got = run(plan, xd, steps)
+        assert np.array_equal(got, ref), (w.shape, steps, np.argwhere(got != ref)[:5])
+
+
+@pytest.mark.parametrize("T", [2, 4])
+def test_f32_fused_aliasing(T):
+    import torch
+    wl = si.workload("1d3p_10240000", small=True)
+    xd, _ = to_dev(wl["make_grid"](np.float32), "f32")
+    plan = sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, time_block=T)
+    keep = xd.clone()
+    for steps in (T, T + 1, 3 * T):
+        y = xd.clone()
+        plan.apply(y, y, steps)
+        assert np.array_equal(from_dev(y), run(plan, xd, steps))
+    assert torch.equal(xd, keep)
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+def test_f32_full_size_equals_single_steps(T):
+    wl = si.workload("1d3p_10240000")
+    xd, _ = to_dev(wl["make_grid"](np.float32), "f32")
+    a = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, time_block=T), xd, 12)
+    b = run(sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, time_block=1), xd, 12)
     assert np.array_equal(a, b)
