@@ -29,10 +29,12 @@ def _mix(carry="f16"):
 
 
 def _alone(wl, xd, steps, carry="f16", engine="sparse"):
-    # batched launches run two fused steps on 2-D paired-band grids (one step otherwise):
-    # they equal the single-plan apply with time_block = 2 bit for bit
+    # batched launches run two fused steps on 2-D paired-band grids and one step on 3-D
+    # grids: they equal the single-plan apply with time_block = 2 (2-D) or 1 (3-D, whose
+    # own two-step kernel sums in another order) bit for bit
     import torch
-    p = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, engine=engine, time_block=2)
+    tb = 2 if len(wl["shape"]) == 2 else 1
+    p = sp.Plan(wl["coeffs"], wl["shape"], carry=carry, engine=engine, time_block=tb)
     y = torch.empty_like(xd)
     p.apply(xd, y, steps)
     return from_dev(y)
