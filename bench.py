@@ -300,30 +300,36 @@ def batch3d_run(torch, sp, si, passes, warmup, with_errors, oracle=None):
     steps = [wl["steps"] for wl in wls]
     npts = sum(int(np.prod(wl["shape"])) * wl["steps"] for wl in wls)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        sp.apply_batch(plans, xs, ys, steps)
-    torch.cuda.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(passes + 1)]
-    evs[0].record(stream)
-    for k in range(passes):
-        sp.apply_batch(plans, xs, ys, steps)
-        evs[k + 1].record(stream)
-    torch.cuda.synchronize()
-    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(passes)]
-    total = evs[0].elapsed_time(evs[-1])
     # the same batch launched step by step (plans without graph replay): the
     # descriptors are staged and the launches enqueued on every call
     direct = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", autotune=True, use_graph=False) for wl in wls]
     ysd = [torch.empty_like(x) for x in xs]
-    sp.apply_batch(direct, xs, ysd, steps)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(passes):
+    for _ in range(warmup):
+        sp.apply_batch(plans, xs, ys, steps)
         sp.apply_batch(direct, xs, ysd, steps)
-    e1.record(stream)
     torch.cuda.synchronize()
-    direct_ms = e0.elapsed_time(e1) / passes
+    # graph replay and direct launches timed in alternating blocks, so that neither
+    # mode is measured alone while the clocks are still settling
+    per, total, direct_total = [], 0.0, 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for block in (passes // 2, passes - passes // 2):  # the passes, in two blocks
+        if block == 0:
+            continue
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(block + 1)]
+        evs[0].record(stream)
+        for k in range(block):
+            sp.apply_batch(plans, xs, ys, steps)
+            evs[k + 1].record(stream)
+        torch.cuda.synchronize()
+        per += [evs[k].elapsed_time(evs[k + 1]) for k in range(block)]
+        total += evs[0].elapsed_time(evs[-1])
+        e0.record(stream)
+        for _ in range(block):
+            sp.apply_batch(direct, xs, ysd, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        direct_total += e0.elapsed_time(e1)
+    direct_ms = direct_total / passes
     same = all(bool(torch.equal(a, b)) for a, b in zip(ys, ysd))
     del ysd
     # the same work, each grid alone on its own plan (one step per launch, as batched)
@@ -365,8 +371,10 @@ def batch3d_run(torch, sp, si, passes, warmup, with_errors, oracle=None):
         sp.apply_batch(pc, x32, yc, steps)
     e1.record(stream)
     torch.cuda.synchronize()
-    f32c_value = npts * passes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    f32c_ms = e0.elapsed_time(e1) / passes
+    f32c_value = npts / (f32c_ms * 1e-3) / 1e9
     res = {"value": round(value, 2), "unit": "GStencil/s", "ms_per_pass": round(total / passes, 4),
+           "hbm_compulsory": compulsory_hbm(1, npts, 2, total / passes),
            "latency_ms": {"p50": round(float(np.percentile(per, 50)), 4),
                           "p99": round(float(np.percentile(per, 99)), 4)},
            "graph_replay": True,
@@ -379,7 +387,8 @@ def batch3d_run(torch, sp, si, passes, warmup, with_errors, oracle=None):
            "plain_gpu_fp32": {"value": round(fp32_value, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
                               "speedup_batched_lowp_over_fp32": round(value / fp32_value, 3)},
            "f32_carry_sparse_split3": {"value": round(f32c_value, 2), "unit": "GStencil/s",
-                                       "speedup_over_plain_fp32": round(f32c_value / fp32_value, 3)}}
+                                       "speedup_over_plain_fp32": round(f32c_value / fp32_value, 3),
+                                       "hbm_compulsory": compulsory_hbm(1, npts, 4, f32c_ms)}}
     if with_errors:
         got = [to_host64(torch, y) for y in ys]
         got32 = [to_host64(torch, y) for y in y32]
@@ -449,6 +458,20 @@ def workload_grid(si, name, dtype):
     return _GRIDS[key]
 
 
+def compulsory_hbm(launches, npts, elem, ms_per_pass):
+    """HBM position of a time loop from its compulsory traffic: every launch reads and
+    writes the whole state once (a fused launch keeps its inner steps on chip)."""
+    b = launches * 2 * npts * elem
+    gbs = b / (ms_per_pass * 1e-3) / 1e9
+    return {"bytes_per_pass": int(b), "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes_source": "compulsory: one read and one write of the state per launch"}
+
+
+def run_hbm(info, wl, carry):
+    return compulsory_hbm(info["launches_per_pass"], int(np.prod(wl["shape"])),
+                          {"f16": 2, "bf16": 2, "f32": 4, "f64": 8}[carry], info["ms_per_pass"])
+
+
 def workload_run(torch, sp, si, name, carry, engine, split, passes, stream, keep_result=True):
     """Plan (autotuned) and time `passes` passes of workload `name`; return (GStencil/s,
     plan info, result on the host in fp64 or None, input on the host in fp64)."""
@@ -461,6 +484,8 @@ def workload_run(torch, sp, si, name, carry, engine, split, passes, stream, keep
     p.apply(xd, y, wl["steps"], stream=stream)
     ms, _ = timed_applies(torch, p, xd, y, wl["steps"], passes, stream)
     info = p.info()
+    info["launches_per_pass"] = p.work(wl["steps"])[0]
+    info["ms_per_pass"] = ms / passes
     p.close()
     got = to_host64(torch, y) if keep_result else None
     del xd, y
@@ -477,7 +502,7 @@ def other_configs(torch, sp, si, stream, oracle):
     v16, i16, g16, x16 = workload_run(torch, sp, si, name, "f16", "sparse", 2, 3, stream)
     e16 = full_grid_error(oracle, wl["coeffs"], x16, wl["steps"], g16, "f16")
     del g16, x16
-    v32, _, g32, x32 = workload_run(torch, sp, si, name, "f32", "direct", 2, 3, stream)
+    v32, i32, g32, x32 = workload_run(torch, sp, si, name, "f32", "direct", 2, 3, stream)
     vs3, is3, gs3, _ = workload_run(torch, sp, si, name, "f32", "sparse", 3, 3, stream)
     ref32 = oracle.apply(wl["coeffs"], x32, wl["steps"])
     e32 = full_grid_error(oracle, wl["coeffs"], x32, wl["steps"], g32, "f32", ref32)
@@ -485,15 +510,15 @@ def other_configs(torch, sp, si, stream, oracle):
     del ref32
     del g32, gs3, x32
     out[name] = {"f16_sparse": {"value": round(v16, 2), "time_steps_per_launch": i16["time_block"],
-                                "error_vs_fp64_oracle": e16},
+                                "error_vs_fp64_oracle": e16, "hbm_compulsory": run_hbm(i16, wl, "f16")},
                  "plain_gpu_fp32": {"value": round(v32, 2), "engine": "direct (VALU fp32)",
-                                    "error_vs_fp64_oracle": e32},
+                                    "error_vs_fp64_oracle": e32, "hbm_compulsory": run_hbm(i32, wl, "f32")},
                  "f32_carry_sparse_split3": {"value": round(vs3, 2), "time_steps_per_launch": is3["time_block"],
-                                             "error_vs_fp64_oracle": es3},
+                                             "error_vs_fp64_oracle": es3, "hbm_compulsory": run_hbm(is3, wl, "f32")},
                  "speedup_f16_over_plain_fp32": round(v16 / v32, 3),
                  "speedup_f32_carry_over_plain_fp32": round(vs3 / v32, 3)}
     # Box-3D27P 512^3 + Heat-3D 256^3 in one batched launch per step
-    out["batch3d"] = batch3d_run(torch, sp, si, 5, 1, True, oracle)
+    out["batch3d"] = batch3d_run(torch, sp, si, 10, 2, True, oracle)
     # Box-2D9P 256^2, fp64 on the direct engine (latency-bound at this size)
     name = "box2d9p_256_f64"
     wl = si.workload(name)
@@ -510,10 +535,13 @@ def other_configs(torch, sp, si, stream, oracle):
         vf, iff, gf, xf = workload_run(torch, sp, si, name, "f32", "sparse", 3, 5, stream)
         ef = full_grid_error(oracle, wl["coeffs"], xf, wl["steps"], gf, "f32s3")
         del gf, xf
+        # (the 1-D lines, 20 and 41 MB, stay in the last-level cache between launches)
         modes = {"f16_sparse": {"value": round(v1, 2), "time_steps_per_launch": i1["time_block"],
-                                "tile_h2": i1["tile_h2"], "error_vs_fp64_oracle": e1},
+                                "tile_h2": i1["tile_h2"], "error_vs_fp64_oracle": e1,
+                                "hbm_compulsory": run_hbm(i1, wl, "f16")},
                  "f32_carry_sparse_split3": {"value": round(vf, 2), "time_steps_per_launch": iff["time_block"],
-                                             "tile_h2": iff["tile_h2"], "error_vs_fp64_oracle": ef}}
+                                             "tile_h2": iff["tile_h2"], "error_vs_fp64_oracle": ef,
+                                             "hbm_compulsory": run_hbm(iff, wl, "f32")}}
         # the config's value: the fastest mode whose error meets its stated bound
         ok = [(m["value"], k) for k, m in modes.items() if m["error_vs_fp64_oracle"]["pass"]]
         best = max(ok)[1] if ok else None
@@ -688,14 +716,15 @@ def main():
         if len(shape) == 2 and args.carry in ("f16", "bf16"):
             # the plain fp32 GPU path and the fp32 carry on the sparse engine (every input
             # value split into 16-bit hi + lo operands, split 3), same workload
-            v32, _, g32, x32h = workload_run(torch, sp, si, args.workload, "f32", "direct", 2, 3, stream)
+            v32, i32, g32, x32h = workload_run(torch, sp, si, args.workload, "f32", "direct", 2, 3, stream)
             out["plain_gpu_fp32"] = {"value": round(v32, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
-                                     "speedup_lowp_over_fp32": round(value / v32, 3)}
+                                     "speedup_lowp_over_fp32": round(value / v32, 3),
+                                     "hbm_compulsory": run_hbm(i32, wl, "f32")}
             del g32
             vm, im, gm, _ = workload_run(torch, sp, si, args.workload, "f32", "sparse", 3, 3, stream)
             out["f32_carry_sparse_split3"] = {
                 "value": round(vm, 2), "unit": "GStencil/s", "time_steps_per_launch": im["time_block"],
-                "tile_h": im["tile_h2"] or im["tile_h"],
+                "tile_h": im["tile_h2"] or im["tile_h"], "hbm_compulsory": run_hbm(im, wl, "f32"),
                 "error_vs_fp64_oracle": full_grid_error(oracle, wl["coeffs"], x32h, T, gm, "f32s3"),
                 "speedup_over_plain_fp32": round(vm / v32, 3)}
             del gm, x32h

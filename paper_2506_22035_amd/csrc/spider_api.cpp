@@ -806,6 +806,43 @@ static uint64_t pair_launch_instructions(const spider_plan_s* p, const BandGrid&
   return iters * (uint64_t)g.nstrips * per_iter;
 }
 
+// 1-D lines: every wave streams whole bodies of U blocks (8; 4 for the fused fp32
+// kernel) over its nb output blocks, plus 3 (T - 1) halo blocks when T steps are
+// fused; each iteration issues T band products per LDS row (hi, and lo with the
+// input split), one smfmac or two dense mfma each.
+static uint64_t line_launch_instructions(const spider_plan_s* p, const BandGrid& g, int T) {
+  const bool f32 = p->carry == SPIDER_F32;
+  const int U = (f32 && T > 1) ? 4 : 8;
+  const int ns = (f32 && p->split == 3) ? 2 : 1;
+  uint64_t iters = 0;
+  for (int w = 0; w < g.nsegs_y; ++w) {
+    const int nb = std::min(g.seg_h, g.nstrips - w * g.seg_h);
+    const int nit = T > 1 ? nb + 3 * (T - 1) : nb;
+    iters += (uint64_t)((nit + U - 1) / U) * U;
+  }
+  return iters * (uint64_t)T * ns * (p->engine == SPIDER_ENGINE_DENSE ? 2 : 1);
+}
+
+// 3-D grids, one step: every workgroup (strip, block of 4 lines, plane segment)
+// streams its planes plus 2r halo planes, padded to a multiple of 2r + 1; each plane
+// issues one band product per output line and kernel row of the instantiated row
+// set (the 2r + 1 rows through the axis for star-shaped row sets, all (2r + 1)^2
+// otherwise).
+static uint64_t volume_launch_instructions(const spider_plan_s* p, const BandGrid& g) {
+  const int rr = 2 * p->r + 1;
+  uint32_t star = 0;
+  for (int dz = 0; dz < rr; ++dz)
+    for (int dy = 0; dy < rr; ++dy)
+      if (dz == p->r || dy == p->r) star |= 1u << (dz * rr + dy);
+  const int rows = (p->rowmask & ~star) == 0 ? __builtin_popcount(star) : rr * rr;
+  uint64_t planes = 0;
+  for (int sz = 0; sz < g.nsegs_z; ++sz) {
+    const int hz = std::min(g.seg_h, p->nz - sz * g.seg_h);
+    planes += (uint64_t)((hz + 2 * p->r + rr - 1) / rr) * rr;
+  }
+  return planes * (uint64_t)g.nstrips * g.nsegs_y * rows * kRowsY3 * (p->engine == SPIDER_ENGINE_DENSE ? 2 : 1);
+}
+
 spider_status spider_plan_work(spider_plan_t p, int steps, uint64_t* launches, uint64_t* matrix_instructions) {
   clear_err();
   if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
@@ -816,15 +853,25 @@ spider_status spider_plan_work(spider_plan_t p, int steps, uint64_t* launches, u
   if (!matrix_instructions) return SPIDER_OK;
   *matrix_instructions = 0;
   if (p->engine == SPIDER_ENGINE_DIRECT || total == 0) return SPIDER_OK;
-  if (!(p->band_h == 8 && p->carry == p->operand))
+  const bool pair16 = p->band_h == 8 && p->carry == p->operand;
+  const bool line = p->ndim == 1;
+  const bool volume = p->ndim == 3 && p->carry == p->operand && p->time_block == 1;
+  if (!pair16 && !line && !volume)
     return fail(SPIDER_ERR_UNSUPPORTED, "matrix instruction counts are kept for paired-line bands with a 16-bit "
-                                        "carry only");
+                                        "carry, 1-D lines and 3-D grids at one step per launch with a 16-bit carry");
   uint64_t n = 0;
   for (int k = 1; k <= total; ++k) {
     const int kind = L.kind(k);
-    n += kind == 3   ? pair_launch_instructions(p, p->grid_tb2, p->time_block)
-         : kind == 2 ? pair_launch_instructions(p, p->grid_rem2, 2)
-                     : pair_launch_instructions(p, p->grid_template, 1);
+    if (line)
+      n += kind == 3   ? line_launch_instructions(p, p->grid_tb2, p->time_block)
+           : kind == 2 ? line_launch_instructions(p, p->grid_rem2, 2)
+                       : line_launch_instructions(p, p->grid_template, 1);
+    else if (volume)
+      n += volume_launch_instructions(p, p->grid_template);
+    else
+      n += kind == 3   ? pair_launch_instructions(p, p->grid_tb2, p->time_block)
+           : kind == 2 ? pair_launch_instructions(p, p->grid_rem2, 2)
+                       : pair_launch_instructions(p, p->grid_template, 1);
   }
   *matrix_instructions = n;
   return SPIDER_OK;
