@@ -383,7 +383,10 @@ def batch3d_run(torch, sp, si, passes, warmup, with_errors, oracle=None):
                                "identical_to_graph_replay": same},
            "separate_plans": {"ms_per_pass": round(seq_ms, 4),
                               "GStencil/s": round(npts / (seq_ms * 1e-3) / 1e9, 2),
-                              "tile_h": [p.info()["tile_h"] for p in solo]},
+                              "tile_h": [p.info()["tile_h"] for p in solo],
+                              "hbm_compulsory": compulsory_hbm(1, npts, 2, seq_ms),
+                              "mfma": run_mfma({"ms_per_pass": seq_ms, "matrix_instructions_per_pass": sum(
+                                  p.work(st)[1] or 0 for p, st in zip(solo, steps))})},
            "plain_gpu_fp32": {"value": round(fp32_value, 2), "unit": "GStencil/s", "engine": "direct (VALU fp32)",
                               "speedup_batched_lowp_over_fp32": round(value / fp32_value, 3)},
            "f32_carry_sparse_split3": {"value": round(f32c_value, 2), "unit": "GStencil/s",
@@ -472,6 +475,17 @@ def run_hbm(info, wl, carry):
                           {"f16": 2, "bf16": 2, "f32": 4, "f64": 8}[carry], info["ms_per_pass"])
 
 
+def run_mfma(info):
+    """Matrix-pipe position of a time loop: its matrix instructions (spider_plan_work)
+    x 16 x 16 x 32 multiply-adds x 2 over the pass time, against the published peak;
+    None where the library keeps no count for the plan."""
+    n = info.get("matrix_instructions_per_pass")
+    if not n:
+        return None
+    tf = n * MACS_PER_INSTRUCTION * 2 / (info["ms_per_pass"] * 1e-3) / 1e12
+    return {"instructions_per_pass": int(n), "TFLOPs": round(tf, 1), "frac": round(tf / MFMA_PEAK_TFLOPS, 4)}
+
+
 def workload_run(torch, sp, si, name, carry, engine, split, passes, stream, keep_result=True):
     """Plan (autotuned) and time `passes` passes of workload `name`; return (GStencil/s,
     plan info, result on the host in fp64 or None, input on the host in fp64)."""
@@ -484,7 +498,7 @@ def workload_run(torch, sp, si, name, carry, engine, split, passes, stream, keep
     p.apply(xd, y, wl["steps"], stream=stream)
     ms, _ = timed_applies(torch, p, xd, y, wl["steps"], passes, stream)
     info = p.info()
-    info["launches_per_pass"] = p.work(wl["steps"])[0]
+    info["launches_per_pass"], info["matrix_instructions_per_pass"] = p.work(wl["steps"])
     info["ms_per_pass"] = ms / passes
     p.close()
     got = to_host64(torch, y) if keep_result else None
@@ -510,7 +524,8 @@ def other_configs(torch, sp, si, stream, oracle):
     del ref32
     del g32, gs3, x32
     out[name] = {"f16_sparse": {"value": round(v16, 2), "time_steps_per_launch": i16["time_block"],
-                                "error_vs_fp64_oracle": e16, "hbm_compulsory": run_hbm(i16, wl, "f16")},
+                                "error_vs_fp64_oracle": e16, "hbm_compulsory": run_hbm(i16, wl, "f16"),
+                                "mfma": run_mfma(i16)},
                  "plain_gpu_fp32": {"value": round(v32, 2), "engine": "direct (VALU fp32)",
                                     "error_vs_fp64_oracle": e32, "hbm_compulsory": run_hbm(i32, wl, "f32")},
                  "f32_carry_sparse_split3": {"value": round(vs3, 2), "time_steps_per_launch": is3["time_block"],
@@ -538,10 +553,10 @@ def other_configs(torch, sp, si, stream, oracle):
         # (the 1-D lines, 20 and 41 MB, stay in the last-level cache between launches)
         modes = {"f16_sparse": {"value": round(v1, 2), "time_steps_per_launch": i1["time_block"],
                                 "tile_h2": i1["tile_h2"], "error_vs_fp64_oracle": e1,
-                                "hbm_compulsory": run_hbm(i1, wl, "f16")},
+                                "hbm_compulsory": run_hbm(i1, wl, "f16"), "mfma": run_mfma(i1)},
                  "f32_carry_sparse_split3": {"value": round(vf, 2), "time_steps_per_launch": iff["time_block"],
                                              "tile_h2": iff["tile_h2"], "error_vs_fp64_oracle": ef,
-                                             "hbm_compulsory": run_hbm(iff, wl, "f32")}}
+                                             "hbm_compulsory": run_hbm(iff, wl, "f32"), "mfma": run_mfma(iff)}}
         # the config's value: the fastest mode whose error meets its stated bound
         ok = [(m["value"], k) for k, m in modes.items() if m["error_vs_fp64_oracle"]["pass"]]
         best = max(ok)[1] if ok else None
