@@ -309,7 +309,7 @@ hipError_t launch_band1d(int r, int operand, int engine, const BandGrid& g, hipS
 // T single steps bit for bit.  A wave owning output blocks [b0, b0 + nb)
 // starts at input block s0 = b0 - (T - 1); the extra blocks at both ends are
 // computed for their neighbours and not stored.
-template <int R, int OP, int ENG, bool ALIGNED, int T>
+template <int R, int OP, int ENG, bool ALIGNED, int T, bool EDGE>
 __device__ __forceinline__ void band1d_tbt_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int U = 8;  // input blocks staged per body (a multiple of the ring size 4)
   const int lane = threadIdx.x;
@@ -390,13 +390,15 @@ __device__ __forceinline__ void band1d_tbt_body(const BandGrid& g, int w, uint32
         const int k = s0 + it - 2 * t;
         const int x = 256 * k + ox;
         uint2 v = pack_out<OP>(acc[t]);
-        uint32_t m0 = 0, m1 = 0;
-        if (x >= 0 && x < nx) m0 |= 0x0000ffffu;
-        if (x + 1 >= 0 && x + 1 < nx) m0 |= 0xffff0000u;
-        if (x + 2 >= 0 && x + 2 < nx) m1 |= 0x0000ffffu;
-        if (x + 3 >= 0 && x + 3 < nx) m1 |= 0xffff0000u;
-        v.x &= m0;
-        v.y &= m1;
+        if constexpr (EDGE) {
+          uint32_t m0 = 0, m1 = 0;
+          if (x >= 0 && x < nx) m0 |= 0x0000ffffu;
+          if (x + 1 >= 0 && x + 1 < nx) m0 |= 0xffff0000u;
+          if (x + 2 >= 0 && x + 2 < nx) m1 |= 0x0000ffffu;
+          if (x + 3 >= 0 && x + 3 < nx) m1 |= 0xffff0000u;
+          v.x &= m0;
+          v.y &= m1;
+        }
         uint32_t* lev = ring + t * 4 * kLdsRowDw;
         const int rho = q - 2 * t;
         *reinterpret_cast<uint2*>(lev + (rho & 3) * kLdsRowDw + wmain) = v;
@@ -418,7 +420,14 @@ template <int R, int OP, int ENG, bool ALIGNED, int T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ALIGNED ? 3 : 2))) void band1d_tbt_kernel(BandGrid g) {
   __shared__ uint32_t lds[8 * kLdsRowDw + kLdsSpareDw + (T - 1) * 4 * kLdsRowDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
-  band1d_tbt_body<R, OP, ENG, ALIGNED, T>(g, w, lds);
+  // interior waves (every block they use lies inside the line) skip the zeroing of
+  // intermediate values outside [0, nx)
+  const int s0 = w * g.seg_h - (T - 1);
+  const int nin = min(g.seg_h, g.nstrips - w * g.seg_h) + 2 * (T - 1);
+  if (256 * s0 - 16 >= 0 && 256 * (s0 + nin) + 256 <= g.nx)
+    band1d_tbt_body<R, OP, ENG, ALIGNED, T, false>(g, w, lds);
+  else
+    band1d_tbt_body<R, OP, ENG, ALIGNED, T, true>(g, w, lds);
 }
 
 template <int OP, int ENG, bool AL, int T>

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XLO ? 2 : 3)
 // a single fp32-carry step splits its fp32 input after loading it, and zero
 // outside the line; so each output equals that of T single steps bit for bit,
 // while the grid crosses HBM once per launch instead of once per step.
-template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T>
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T, bool EDGE>
 __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, uint32_t* lds) {
   constexpr int U = 4;             // input blocks staged per body (the ring size)
   constexpr int NS = XLO ? 2 : 1;  // LDS rows per level of a block: hi (and lo)
@@ -408,11 +408,13 @@ __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, ui
         // previous row's tail and the next row's head (ring slots by iteration)
         // (the whole vector is cast first: element-wise casts of a float vector have been
         // seen to compile to four copies of element 0)
-        const int x = 256 * (s0 + it - 2 * t) + ox;
         u32x4 v = __builtin_bit_cast(u32x4, acc[t]);
+        if constexpr (EDGE) {
+          const int x = 256 * (s0 + it - 2 * t) + ox;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (x + e < 0 || x + e >= nx) v[e] = 0u;
+          for (int e = 0; e < 4; ++e)
+            if (x + e < 0 || x + e >= nx) v[e] = 0u;
+        }
         uint32_t h0, l0, h1, l1;
         split2<OP, XLO>(v.x, v.y, &h0, &l0);
         split2<OP, XLO>(v.z, v.w, &h1, &l1);
@@ -443,7 +445,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ba
   constexpr int NS = XLO ? 2 : 1;
   __shared__ uint32_t lds[4 * NS * kLdsRowDw + 64 + (T - 1) * 4 * NS * kLdsRowDw];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
-  band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T>(g, w, lds);
+  // interior waves (every block they use lies inside the line) skip the zeroing of
+  // intermediate values outside [0, nx)
+  const int s0 = w * g.seg_h - (T - 1);
+  const int nin = min(g.seg_h, g.nstrips - w * g.seg_h) + 2 * (T - 1);
+  if (256 * s0 - 16 >= 0 && 256 * (s0 + nin) + 256 <= g.nx)
+    band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T, false>(g, w, lds);
+  else
+    band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T, true>(g, w, lds);
 }
 
 // ----------------------------------------------------------------------------- 3-D
