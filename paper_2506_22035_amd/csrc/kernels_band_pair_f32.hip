@@ -284,7 +284,7 @@ __device__ __forceinline__ void band2d_pair_f32_body12(const BandGrid& g, int w,
 // stream with T levels, each fused level reading the previous level's two-slot
 // ring.  (One and two steps keep the body above, whose register allocation for a
 // single step stays within the 4-wave budget.)
-template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T>
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T, bool EDGE>
 __device__ __forceinline__ void band2d_pair_f32_bodyT(const BandGrid& g, int w, uint32_t* lds) {
   static_assert(T >= 3, "one and two steps use band2d_pair_f32_body12");
   constexpr int NP = R + 1;
@@ -412,14 +412,22 @@ __device__ __forceinline__ void band2d_pair_f32_bodyT(const BandGrid& g, int w, 
       // split, keep it for pass t + 1 at the next iteration
 #pragma unroll
       for (int t = 0; t + 1 < T; ++t) {
-        const int mrow = y0 - (T - 1 - t) * R + phi + 2 * (P - t * (R + 1) - R);
-        const uint32_t rmask = (mrow >= 0 && mrow < ny) ? 0xffffffffu : 0u;
-        const u32x4 va = __builtin_bit_cast(u32x4, acc_a[t][fs]), vb = __builtin_bit_cast(u32x4, acc_b[t][fs]);
+        u32x4 va = __builtin_bit_cast(u32x4, acc_a[t][fs]), vb = __builtin_bit_cast(u32x4, acc_b[t][fs]);
+        if constexpr (EDGE) {
+          // (interior waves compute only rows and columns inside the grid)
+          const int mrow = y0 - (T - 1 - t) * R + phi + 2 * (P - t * (R + 1) - R);
+          const uint32_t rmask = (mrow >= 0 && mrow < ny) ? 0xffffffffu : 0u;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            va[e] &= ma[e] & rmask;
+            vb[e] &= mb[e] & rmask;
+          }
+        }
         uint32_t ha0, la0, ha1, la1, hb0, lb0, hb1, lb1;
-        split_pair<OP, XLO>(va.x & ma[0] & rmask, va.y & ma[1] & rmask, &ha0, &la0);
-        split_pair<OP, XLO>(va.z & ma[2] & rmask, va.w & ma[3] & rmask, &ha1, &la1);
-        split_pair<OP, XLO>(vb.x & mb[0] & rmask, vb.y & mb[1] & rmask, &hb0, &lb0);
-        split_pair<OP, XLO>(vb.z & mb[2] & rmask, vb.w & mb[3] & rmask, &hb1, &lb1);
+        split_pair<OP, XLO>(va.x, va.y, &ha0, &la0);
+        split_pair<OP, XLO>(va.z, va.w, &ha1, &la1);
+        split_pair<OP, XLO>(vb.x, vb.y, &hb0, &lb0);
+        split_pair<OP, XLO>(vb.z, vb.w, &hb1, &lb1);
         uint32_t* mc = mid + (t * 2 + (P & 1)) * PAIRSZ;
         *reinterpret_cast<uint2*>(mc + mwo) = make_uint2(ha0, ha1);
         *reinterpret_cast<uint2*>(mc + mwo + kPairHalfDw) = make_uint2(hb0, hb1);
@@ -440,10 +448,19 @@ void band2d_pair_f32_kernel(BandGrid g) {
   constexpr int PAIRSZ = 2 * (XLO ? 2 : 1) * kPairRowDw;
   __shared__ uint32_t lds[2 * T * PAIRSZ];
   const int w = xcd_remap(blockIdx.x, gridDim.x);
-  if constexpr (T <= 2)
+  if constexpr (T <= 2) {
     band2d_pair_f32_body12<R, OP, ENG, ALIGNED, XLO, T == 2>(g, w, lds);
-  else
-    band2d_pair_f32_bodyT<R, OP, ENG, ALIGNED, XLO, T>(g, w, lds);
+  } else {
+    // interior waves (columns [xp, xp + 256) and rows [y0 - T r, y0 + hrows + T r + 2)
+    // inside the grid) skip the zeroing of intermediate values outside it
+    const int strip = w % g.nstrips, seg = w / g.nstrips;
+    const int xp = strip * pair_tb_width(T, R) - pair_tb_margin(T, R);
+    const int y0 = seg * g.seg_h, hrows = min(g.seg_h, g.ny - y0);
+    if (xp >= 0 && xp + 256 <= g.nx && y0 - T * R >= 0 && y0 + hrows + T * R + 2 <= g.ny)
+      band2d_pair_f32_bodyT<R, OP, ENG, ALIGNED, XLO, T, false>(g, w, lds);
+    else
+      band2d_pair_f32_bodyT<R, OP, ENG, ALIGNED, XLO, T, true>(g, w, lds);
+  }
 }
 
 namespace {
