@@ -270,11 +270,11 @@ spider_status autotune_tile(spider_plan_s* p) {
       set_tile2(p, best2);
     }
   }
-  if (s) hipStreamSynchronize(s);
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  if (s) hipStreamDestroy(s);
-  hipFree(tmp);
+  if (s) (void)hipStreamSynchronize(s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) (void)hipStreamDestroy(s);
+  (void)hipFree(tmp);
   if (e != hipSuccess) return hip_fail(e, "autotune");
   std::lock_guard<std::mutex> lk(g_mu);
   g_cache[k] = best;

@@ -53,12 +53,12 @@ struct BatchArena {
   ~BatchArena() { release(); }
   void release() {
     if (done) {
-      hipEventSynchronize(done);
-      hipEventDestroy(done);
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
       done = nullptr;
     }
-    if (host) hipHostFree(host);
-    if (dev) hipFree(dev);
+    if (host) (void)hipHostFree(host);
+    if (dev) (void)hipFree(dev);
     host = nullptr;
     dev = nullptr;
     cap = 0;
@@ -74,8 +74,8 @@ struct BatchArena {
       if (e != hipSuccess) return e;
     }
     if (bytes <= cap) return hipSuccess;
-    if (host) hipHostFree(host);
-    if (dev) hipFree(dev);
+    if (host) (void)hipHostFree(host);
+    if (dev) (void)hipFree(dev);
     host = nullptr;
     dev = nullptr;
     cap = 0;
@@ -332,8 +332,8 @@ void release_entry(BatchGraphEntry& en) {
   (void)hipGetDevice(&cur);
   if (cur != en.device) (void)hipSetDevice(en.device);
   (void)hipDeviceSynchronize();  // a replay may still read the descriptors
-  if (en.exec) hipGraphExecDestroy(en.exec);
-  if (en.dev_desc) hipFree(en.dev_desc);
+  if (en.exec) (void)hipGraphExecDestroy(en.exec);
+  if (en.dev_desc) (void)hipFree(en.dev_desc);
   if (cur != en.device) (void)hipSetDevice(cur);
   en.exec = nullptr;
   en.dev_desc = nullptr;
@@ -377,16 +377,16 @@ static spider_status enqueue_batch_graph(const std::vector<BatchItem>& items, in
       if (e == hipSuccess && !cs) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
       if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) {
-        hipFree(en.dev_desc);
+        (void)hipFree(en.dev_desc);
         return hip_fail(e, "batch graph set-up");
       }
       st = enqueue_launches(P, en.dev_desc, cs);
       hipGraph_t graph = nullptr;
       e = hipStreamEndCapture(cs, &graph);
       if (st == SPIDER_OK && e == hipSuccess) e = hipGraphInstantiate(&en.exec, graph, nullptr, nullptr, 0);
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       if (st != SPIDER_OK || e != hipSuccess) {
-        hipFree(en.dev_desc);
+        (void)hipFree(en.dev_desc);
         return st != SPIDER_OK ? st : hip_fail(e, "batch graph capture");
       }
     }
@@ -487,7 +487,7 @@ void* take_scratch(spider_server_s* S, size_t bytes) {
   while (S->used + S->pooled + 2 * bytes > S->budget && S->pooled > 0) {
     for (auto& kv : S->pool) {
       if (!kv.second.empty()) {
-        hipFree(kv.second.back());
+        (void)hipFree(kv.second.back());
         kv.second.pop_back();
         S->pooled -= kv.first;
         break;
@@ -498,7 +498,7 @@ void* take_scratch(spider_server_s* S, size_t bytes) {
   if (hipMalloc(&p, bytes) == hipSuccess) return p;
   // the device is short of memory: return every idle buffer and try once more
   for (auto& kv : S->pool)
-    for (void* q : kv.second) hipFree(q);
+    for (void* q : kv.second) (void)hipFree(q);
   S->pool.clear();
   S->pooled = 0;
   p = nullptr;
@@ -534,7 +534,7 @@ void finish(spider_server_s* S, ServerRequest* r, spider_status st) {
 }
 
 void server_loop(spider_server_s* S) {
-  hipSetDevice(S->device);
+  (void)hipSetDevice(S->device);
   for (;;) {
     std::vector<ServerRequest*> round;
     {
@@ -764,9 +764,9 @@ spider_status spider_server_destroy(spider_server_t S) {
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
   for (auto& kv : S->pool)
-    for (void* p : kv.second) hipFree(p);
+    for (void* p : kv.second) (void)hipFree(p);
   for (auto& kv : S->tickets) delete kv.second;
-  if (S->stream) hipStreamDestroy(S->stream);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
   delete S;
   return SPIDER_OK;
 }

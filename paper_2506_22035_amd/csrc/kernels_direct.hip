@@ -324,10 +324,8 @@ __global__ __launch_bounds__(256) void direct1d_kernel(const T* __restrict__ in,
     const uint32_t off = (uint32_t)((x0 - R + t) * (int)sizeof(T));  // negative wraps out of range
     if constexpr (sizeof(T) == 4)
       v[t] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-    else {
-      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    else
       v[t] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-    }
   }
   T c[2 * R + 1];
 #pragma unroll

@@ -424,12 +424,12 @@ static spider_status capture(spider_plan_s* p, F body, hipGraphExec_t* exec) {
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(p->cap_stream, &graph);
   if (st != SPIDER_OK) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return st;
   }
   if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
   e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   return SPIDER_OK;
 }
@@ -462,8 +462,8 @@ static spider_status enqueue_long(spider_plan_s* p, const void* in, void* out, c
         }, &exec);
         if (st != SPIDER_OK) return st;
         if (p->body_graphs.size() >= 16) {  // bound the cache (rare: waits for queued work first)
-          hipDeviceSynchronize();
-          hipGraphExecDestroy(p->body_graphs.begin()->second);
+          (void)hipDeviceSynchronize();
+          (void)hipGraphExecDestroy(p->body_graphs.begin()->second);
           p->body_graphs.erase(p->body_graphs.begin());
         }
         it = p->body_graphs.emplace(key, exec).first;
@@ -740,8 +740,8 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
     spider_status st = capture(p, [&](hipStream_t cs) { return enqueue_steps(p, in, out, steps, cs); }, &exec);
     if (st != SPIDER_OK) return st;
     if (p->graphs.size() >= 64) {  // bound the cache (rare: waits for queued work first)
-      hipDeviceSynchronize();
-      hipGraphExecDestroy(p->graphs.begin()->second);
+      (void)hipDeviceSynchronize();
+      (void)hipGraphExecDestroy(p->graphs.begin()->second);
       p->graphs.erase(p->graphs.begin());
     }
     it = p->graphs.emplace(key, exec).first;
@@ -754,14 +754,14 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
 spider_status spider_plan_destroy(spider_plan_t p) {
   if (!p) return SPIDER_OK;
   batch_graphs_forget_plan(p);
-  for (auto& kv : p->graphs) hipGraphExecDestroy(kv.second);
-  for (auto& kv : p->body_graphs) hipGraphExecDestroy(kv.second);
-  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
-  if (p->d_apack) hipFree(p->d_apack);
-  if (p->d_ipack) hipFree(p->d_ipack);
-  if (p->d_dpack) hipFree(p->d_dpack);
-  if (p->d_coeffs) hipFree(p->d_coeffs);
-  if (p->d_scratch) hipFree(p->d_scratch);
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : p->body_graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_apack) (void)hipFree(p->d_apack);
+  if (p->d_ipack) (void)hipFree(p->d_ipack);
+  if (p->d_dpack) (void)hipFree(p->d_dpack);
+  if (p->d_coeffs) (void)hipFree(p->d_coeffs);
+  if (p->d_scratch) (void)hipFree(p->d_scratch);
   delete p;
   return SPIDER_OK;
 }
