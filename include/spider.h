@@ -240,18 +240,21 @@ spider_status spider_measure_matrix_rate(int sparse, int waves_per_simd, int ite
 
 /*
  * Batched apply (launches over the tiles of every grid).
- * Runs grids of uneven size and stencil shape together.  Launch k advances
- * every grid that still has work: 2-D grids with paired-line bands by two fused
- * time steps per launch (steps[i] / 2 launches, then one single step when
- * steps[i] is odd), other grids by one step.  The plans must share the carry
- * dtype and use the sparse or dense engine; grids may be 2-D or 3-D.
- * Each grid's result equals spider_apply of a plan with time_block = 2 bit for
- * bit (one step per launch where two cannot be fused; a plan fusing more steps
- * agrees up to rounding).
+ * Runs grids of uneven size and stencil shape together.  Grids whose plan uses a
+ * matrix engine with a 16-bit carry, the implicit row swap and a 2-D radius of 1..3
+ * or a 3-D radius of 1 are batched, one sequence of launches per (carry dtype,
+ * engine): launch k advances every such grid that still has work, 2-D grids with
+ * paired-line bands by two fused time steps per launch (steps[i] / 2 launches, then
+ * one single step when steps[i] is odd), other grids by one step.  Each of their
+ * results equals spider_apply of a plan with time_block = 2 bit for bit (one step
+ * per launch where two cannot be fused; a plan fusing more steps agrees up to
+ * rounding).  Every other plan (the direct engine, an fp32 carry, 1-D lines, larger
+ * radii, the explicit row swap) runs its own time loop after them on the same
+ * stream, exactly as spider_apply.
  *   n       number of grids, 1..4096
  *   plans, ins, outs, steps: host arrays of n entries, as for spider_apply.
- * Errors: INVALID (also: a plan of another device than the current one),
- * UNSUPPORTED (mixed carries or direct-engine plans), HIP.
+ * Errors: INVALID (also: a plan of another device than the current one, or one plan
+ * twice), OOM, HIP.
  */
 spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* const* ins,
                                  void* const* outs, const int* steps, void* stream);
@@ -263,9 +266,10 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
  * current HIP device.  Requests are admitted while their device footprint
  * (two grid-sized buffers of the plan's carry dtype) fits in `hbm_budget_bytes`
  * and a slot is free (max_slots); admitted requests share every round's
- * batched launch (2-D grids whose plan fuses three or four steps run their own
- * fused launches in the round instead), and a request that arrives while others
- * run joins at the next round.  Grid state stays on the device between rounds.
+ * batched launch (2-D grids whose plan fuses three or four steps, and plans that
+ * batched apply runs alone, run their own launches in the round instead), and a
+ * request that arrives while others run joins at the next round.  Grid state
+ * stays on the device between rounds.  Any plan spider_apply accepts is accepted.
  */
 spider_status spider_server_create(size_t hbm_budget_bytes, int max_slots, int max_queue,
                                    spider_server_t* out);

@@ -424,10 +424,14 @@ static BatchArena& global_arena(int device) {
 // =========================================================================== server
 
 namespace {
-// Plans that batches and the server run with their own launches: the matrix
-// engines with an fp32 carry (the batched kernel holds 16-bit bodies only).
+// Plans whose grids the batched kernel runs: a matrix engine with a 16-bit carry,
+// 2-D radius 1..3 or 3-D radius 1, the implicit row swap.  Batches and the server
+// run every other plan (direct engine, fp32 carry, 1-D lines, larger radii, the
+// explicit row swap) with its own time loop on the same stream.
 bool runs_alone(const spider_plan_s* p) {
-  return p->carry == SPIDER_F32 && p->engine != SPIDER_ENGINE_DIRECT && p->ndim >= 2;
+  const bool batchable = p->engine != SPIDER_ENGINE_DIRECT && p->carry == p->operand && p->ndim >= 2 &&
+                         !p->row_swap && (p->ndim == 2 ? p->r <= 3 : p->r == 1);
+  return !batchable;
 }
 }  // namespace
 
@@ -623,7 +627,7 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
                                  const int* steps, void* stream) {
   clear_err();
   if (n < 1 || n > 4096 || !plans || !ins || !outs || !steps) return fail(SPIDER_ERR_INVALID, "bad batch arguments");
-  std::vector<BatchItem> items;
+  std::map<int, std::vector<BatchItem>> groups;  // batched grids by (operand dtype, engine)
   std::vector<int> solo;
   for (int i = 0; i < n; ++i) {
     if (!plans[i] || !ins[i] || !outs[i]) return fail(SPIDER_ERR_INVALID, "NULL plan or grid in batch entry %d", i);
@@ -640,17 +644,19 @@ spider_status spider_apply_batch(int n, const spider_plan_t* plans, const void* 
     if (runs_alone(plans[i]))
       solo.push_back(i);
     else
-      items.push_back({plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
+      groups[plans[i]->operand * 8 + plans[i]->engine].push_back(
+          {plans[i], ins[i], outs[i], plans[i]->d_scratch, steps[i]});
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!items.empty()) {
+  for (auto& kv : groups) {
+    const std::vector<BatchItem>& items = kv.second;
     bool graph = true;
     for (const auto& it : items) graph = graph && it.plan->use_graph;
     spider_status st = graph ? enqueue_batch_graph(items, items[0].plan->device, s)
                              : enqueue_batch(global_arena(items[0].plan->device), items, s);
     if (st != SPIDER_OK) return st;
   }
-  // fp32-carry grids run their own time loops on the same stream (as spider_apply)
+  // the other grids run their own time loops on the same stream (as spider_apply)
   for (int i : solo) {
     spider_status st = spider_apply(plans[i], ins[i], outs[i], steps[i], stream);
     if (st != SPIDER_OK) return st;
@@ -683,11 +689,6 @@ spider_status spider_submit(spider_server_t S, spider_plan_t plan, const void* i
                             uint64_t* ticket) {
   clear_err();
   if (!S || !plan || !in || !out || !ticket || steps < 0) return fail(SPIDER_ERR_INVALID, "bad submit arguments");
-  if (!runs_alone(plan) && (plan->engine == SPIDER_ENGINE_DIRECT || plan->carry != plan->operand ||
-                            plan->ndim == 1 || (plan->ndim == 2 ? plan->r > 3 : plan->r != 1) || plan->row_swap))
-    return fail(SPIDER_ERR_UNSUPPORTED,
-                "the server runs matrix-engine plans: 16-bit plans with the implicit row swap (2-D radius 1..3, "
-                "3-D radius 1) and fp32-carry plans (2-D, 3-D)");
   if (plan->device != S->device)
     return fail(SPIDER_ERR_INVALID, "the plan was built on device %d, the server runs on device %d", plan->device,
                 S->device);

@@ -98,13 +98,35 @@ def test_tile_heights_agree_and_aliasing(oracle_mod):
     assert torch.equal(xd, keep)
 
 
-def test_batch_rejects_1d():
+def test_batch_and_server_run_1d_alone():
+    # 1-D lines are not batched: batched apply and the server run them with their
+    # own time loop, so the results equal spider_apply bit for bit
+    import time
     import torch
-    plan = sp.Plan(np.array([0.25, 0.5, 0.25]), (1000,), carry="f16")
-    x = torch.zeros(1000, dtype=torch.float16, device="cuda:0")
-    with pytest.raises(sp.SpiderError) as e:
-        sp.apply_batch([plan], [x], [torch.empty_like(x)], [3])
-    assert e.value.status == 2
+    wl = si.workload("1d3p_10240000", small=True)
+    x16, _ = to_dev(wl["make_grid"](), "f16")
+    x32, _ = to_dev(wl["make_grid"](np.float32), "f32")
+    plans = [sp.Plan(wl["coeffs"], wl["shape"], carry="f16", time_block=3),
+             sp.Plan(wl["coeffs"], wl["shape"], carry="f32", engine="sparse", split=3, time_block=2)]
+    xs = [x16, x32]
+    refs = [run(p, x, 7) for p, x in zip(plans, xs)]
+    outs = [torch.empty_like(x) for x in xs]
+    sp.apply_batch(plans, xs, outs, [7, 7])
+    for o, r in zip(outs, refs):
+        assert np.array_equal(from_dev(o), r)
+    srv = sp.Server(1 << 28)
+    try:
+        outs = [torch.empty_like(x) for x in xs]
+        ts = [srv.submit(p, x, o, 7) for p, x, o in zip(plans, xs, outs)]
+        t0 = time.time()
+        while not all(srv.poll(t)[0] for t in ts):
+            assert time.time() - t0 < 60
+            time.sleep(0.001)
+        assert all(srv.poll(t)[1] == 0 for t in ts)
+        for o, r in zip(outs, refs):
+            assert np.array_equal(from_dev(o), r)
+    finally:
+        srv.close()
 
 
 # ------------------------------------------------------------------ fp32 carry on the matrix engines

@@ -83,10 +83,39 @@ def test_batch_rejects_bad_input():
     y = torch.empty_like(xd)
     with pytest.raises(sp.SpiderError):
         sp.apply_batch([p, p], [xd, xd], [y, y], [1, 1])  # one plan twice
-    p32 = sp.Plan(wl["coeffs"], wl["shape"], carry="f32")
-    xf, _ = to_dev(wl["make_grid"](), "f32")
-    with pytest.raises(sp.SpiderError):
-        sp.apply_batch([p32], [xf], [torch.empty_like(xf)], [1])
+
+
+def test_batch_runs_unbatchable_plans_alone_and_groups_carries():
+    # plans the batched kernel does not hold (the direct engine, an fp32 carry, a
+    # radius above 3) run their own time loops; fp16 and bf16 plans are batched in
+    # two groups: every result equals spider_apply of its plan
+    import torch
+    wl = si.workload("box2d49p_10240", small=True)
+    cases = [(dict(carry="f32"), "f32"),                                   # direct engine
+             (dict(carry="f32", engine="sparse", split=3), "f32"),          # fp32 carry
+             (dict(carry="f16"), "f16"), (dict(carry="bf16"), "bf16"),
+             (dict(carry="f16", band_height=16), "f16")]
+    plans, xs, refs = [], [], []
+    for kw, carry in cases:
+        p = sp.Plan(wl["coeffs"], wl["shape"], **kw)
+        xd, _ = to_dev(wl["make_grid"](), carry)
+        y = torch.empty_like(xd)
+        p.apply(xd, y, 5)
+        plans.append(p)
+        xs.append(xd)
+        refs.append(from_dev(y))
+    w9 = si.coeffs_uniform01(2, 4, 3)  # radius 4: 16-point bands, not batched
+    p9 = sp.Plan(w9, (100, 300), carry="f16")
+    x9, _ = to_dev(si.grid_uniform01((100, 300), 4), "f16")
+    y9 = torch.empty_like(x9)
+    p9.apply(x9, y9, 5)
+    plans.append(p9)
+    xs.append(x9)
+    refs.append(from_dev(y9))
+    outs = [torch.empty_like(x) for x in xs]
+    sp.apply_batch(plans, xs, outs, [5] * len(plans))
+    for o, r in zip(outs, refs):
+        assert np.array_equal(from_dev(o), r)
 
 
 def _wait(srv, tickets, timeout=60.0):

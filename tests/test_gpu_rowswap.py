@@ -82,20 +82,30 @@ def test_full_size_box7r_equals_implicit():
     assert np.array_equal(got[0], got[1])
 
 
-def test_batch_and_server_reject_explicit():
+def test_batch_and_server_run_explicit_alone():
+    # the batched kernel holds the implicit swap only: batched apply and the server
+    # run an explicit-swap plan with its own time loop, equal to spider_apply
+    import time
     shape = (64, 64)
     w = si.integer_coeffs(2, 1, -1, 1, 5, "box")
     x = si.grid_integer(shape, -2, 2, 6)
     xd, _ = to_dev(x, "f16")
-    y = empty_like_dev(xd)
     plan = sp.Plan(w, shape, carry="f16", engine="sparse", row_swap="explicit")
-    with pytest.raises(sp.SpiderError) as e:
-        sp.apply_batch([plan], [xd], [y], [1])
-    assert e.value.status == 2
+    ref = empty_like_dev(xd)
+    plan.apply(xd, ref, 3)
+    ref = from_dev(ref)
+    y = empty_like_dev(xd)
+    sp.apply_batch([plan], [xd], [y], [3])
+    assert np.array_equal(from_dev(y), ref)
     srv = sp.Server(1 << 28)
     try:
-        with pytest.raises(sp.SpiderError) as e:
-            srv.submit(plan, xd, y, 1)
-        assert e.value.status == 2
+        y2 = empty_like_dev(xd)
+        t = srv.submit(plan, xd, y2, 3)
+        t0 = time.time()
+        while not srv.poll(t)[0]:
+            assert time.time() - t0 < 60
+            time.sleep(0.001)
+        assert srv.poll(t)[1] == 0
+        assert np.array_equal(from_dev(y2), ref)
     finally:
         srv.close()
