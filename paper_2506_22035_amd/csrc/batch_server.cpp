@@ -442,8 +442,9 @@ struct ServerRequest {
   const void* in = nullptr;
   void* out = nullptr;
   int steps = 0;
-  int remaining = 0;
-  bool started = false;
+  int remaining = 0;   // steps not yet completed on the device
+  int planned = 0;     // of those, steps already enqueued in a round still running
+  bool issued = false; // a first round has been enqueued (later rounds read `out`)
   void* scratch = nullptr;
   size_t footprint = 0;
   std::chrono::steady_clock::time_point t_submit;
@@ -465,7 +466,11 @@ struct spider_server_s {
   std::thread th;
   bool stop = false;
   hipStream_t stream = nullptr;
-  spider_impl::BatchArena arena;
+  // descriptor arenas taken in turn: two rounds of up to two batched groups each can
+  // be in flight, and an arena is reused only after its previous launches finished
+  static constexpr int kArenas = 4;
+  spider_impl::BatchArena arenas[kArenas];
+  int arena_next = 0;
   std::map<size_t, std::vector<void*>> pool;  // idle scratch buffers by size
   size_t pooled = 0;
   std::vector<double> lat_us;  // ring of the most recent completion latencies
@@ -537,14 +542,67 @@ void finish(spider_server_s* S, ServerRequest* r, spider_status st) {
   S->used -= r->footprint;
 }
 
+// One enqueued round: its requests and the steps each advances, and the event that
+// marks its completion on the server stream.
+struct ServerRound {
+  std::vector<ServerRequest*> reqs;
+  std::vector<int> adv;
+  hipEvent_t done = nullptr;
+  spider_status st = SPIDER_OK;
+};
+
+// Enqueue one round: every listed request advances by its step count, one batched
+// time loop per (operand dtype, engine, dimension) group: a launch of one dimension
+// runs the single-class batch kernel, which keeps more waves per SIMD than the
+// kernel holding both the 2-D and 3-D bodies (7-8 % more requests per second on the
+// serving mix than one mixed launch).  Grids whose plan fuses more than the batched
+// launch's two steps (large 2-D grids), and plans the batched kernel does not hold,
+// run their own launches instead, with the request's scratch buffer.
+spider_status enqueue_round(spider_server_s* S, ServerRound& R) {
+  std::map<int, std::vector<spider_impl::BatchItem>> groups;
+  std::vector<spider_impl::BatchItem> solo;
+  for (size_t i = 0; i < R.reqs.size(); ++i) {
+    ServerRequest* r = R.reqs[i];
+    const spider_impl::BatchItem it{r->plan, r->issued ? r->out : r->in, r->out, r->scratch, R.adv[i]};
+    if ((r->plan->time_block > 2 && r->plan->ndim == 2) || runs_alone(r->plan))
+      solo.push_back(it);
+    else
+      groups[(r->plan->operand * 8 + r->plan->engine) * 4 + r->plan->ndim].push_back(it);
+  }
+  for (auto& kv : groups) {
+    spider_impl::BatchArena& A = S->arenas[S->arena_next];
+    S->arena_next = (S->arena_next + 1) % spider_server_s::kArenas;
+    spider_status st = spider_impl::enqueue_batch(A, kv.second, S->stream);
+    if (st != SPIDER_OK) return st;
+  }
+  for (const auto& it : solo) {
+    spider_status st = spider_impl::enqueue_steps_scratch(it.plan, it.in, it.out, it.scratch, it.steps, S->stream);
+    if (st != SPIDER_OK) return st;
+  }
+  return hipEventRecord(R.done, S->stream) == hipSuccess ? SPIDER_OK : SPIDER_ERR_HIP;
+}
+
+// Rounds are pipelined: round k + 1 is built and enqueued (behind round k on the same
+// stream) before the loop waits for round k, so the device does not idle while the
+// host finishes round k's requests and admits new ones.  A request takes part in a
+// round only with steps left beyond those already enqueued; its state moves between
+// rounds in its own buffers in stream order.
 void server_loop(spider_server_s* S) {
   (void)hipSetDevice(S->device);
+  ServerRound rounds[2];
+  for (auto& R : rounds) (void)hipEventCreateWithFlags(&R.done, hipEventDisableTiming);
+  ServerRound* pending = nullptr;  // enqueued, not yet waited for
+  int next = 0;
   for (;;) {
-    std::vector<ServerRequest*> round;
+    ServerRound& R = rounds[next];
+    R.reqs.clear();
+    R.adv.clear();
+    R.st = SPIDER_OK;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
-      if (S->stop && S->active.empty()) break;
+      if (!pending)
+        S->cv.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop && S->active.empty() && !pending) break;
       // admission: FIFO while a slot is free and the footprint fits the budget
       while (!S->stop && !S->queue.empty() && (int)S->active.size() < S->max_slots) {
         ServerRequest* r = S->queue.front();
@@ -565,58 +623,63 @@ void server_loop(spider_server_s* S) {
         S->used += r->footprint;
         S->active.push_back(r);
       }
-      round = S->active;
+      for (ServerRequest* r : S->active) {
+        if (r->done) continue;
+        const int k = std::min(r->remaining - r->planned, S->round_steps);
+        if (k > 0 || !r->issued) {  // (a request of zero steps runs once, as a copy)
+          R.reqs.push_back(r);
+          R.adv.push_back(k);
+        }
+      }
     }
-    if (round.empty()) {
-      std::unique_lock<std::mutex> lk(S->mu);
-      S->cv.wait_for(lk, std::chrono::milliseconds(1));
-      continue;
+    if (!R.reqs.empty()) {
+      R.st = enqueue_round(S, R);
+      for (size_t i = 0; i < R.reqs.size(); ++i) {
+        R.reqs[i]->planned += R.adv[i];
+        R.reqs[i]->issued = true;
+      }
     }
-    // one round: every admitted request advances by up to round_steps steps, one
-    // batched time loop per (operand dtype, engine, dimension) group: a launch of
-    // one dimension runs the single-class batch kernel, which keeps more waves per
-    // SIMD than the kernel holding both the 2-D and 3-D bodies (7-8 % more
-    // requests per second on the serving mix than one mixed launch).  Grids whose plan fuses
-    // more than the batched launch's two steps (large 2-D grids) run their own
-    // fused launches instead, with the request's scratch buffer.
-    std::vector<int> adv;
-    std::map<int, std::vector<spider_impl::BatchItem>> groups;
-    std::vector<spider_impl::BatchItem> solo;
-    for (ServerRequest* r : round) {
-      const int k = std::min(r->remaining, S->round_steps);
-      const spider_impl::BatchItem it{r->plan, r->started ? r->out : r->in, r->out, r->scratch, k};
-      if ((r->plan->time_block > 2 && r->plan->ndim == 2) || runs_alone(r->plan))
-        solo.push_back(it);
-      else
-        groups[(r->plan->operand * 8 + r->plan->engine) * 4 + r->plan->ndim].push_back(it);
-      adv.push_back(k);
-    }
-    spider_status st = SPIDER_OK;
-    for (auto& kv : groups) {
-      st = spider_impl::enqueue_batch(S->arena, kv.second, S->stream);
-      if (st != SPIDER_OK) break;
-    }
-    for (size_t i = 0; st == SPIDER_OK && i < solo.size(); ++i)
-      st = spider_impl::enqueue_steps_scratch(solo[i].plan, solo[i].in, solo[i].out, solo[i].scratch, solo[i].steps,
-                                              S->stream);
-    if (st == SPIDER_OK && hipStreamSynchronize(S->stream) != hipSuccess) st = SPIDER_ERR_HIP;
-    std::lock_guard<std::mutex> lk(S->mu);
-    std::vector<ServerRequest*> still;
-    for (size_t i = 0; i < round.size(); ++i) {
-      ServerRequest* r = round[i];
-      if (st != SPIDER_OK) {
-        finish(S, r, st);
+    if (!pending) {
+      if (R.reqs.empty()) {  // nothing admitted and nothing in flight
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait_for(lk, std::chrono::milliseconds(1));
         continue;
       }
-      r->started = true;
-      r->remaining -= adv[i];
-      if (r->remaining <= 0)
-        finish(S, r, SPIDER_OK);
-      else
-        still.push_back(r);
+      pending = &R;  // the next pass enqueues the following round before waiting
+      next ^= 1;
+      continue;
     }
-    S->active.swap(still);
+    // wait for the round in flight and finish what it completed
+    ServerRound* W = pending;
+    if (W->st == SPIDER_OK && hipEventSynchronize(W->done) != hipSuccess) W->st = SPIDER_ERR_HIP;
+    // (after a failure, a later round of the same requests may still be queued: let
+    // the stream drain before their buffers are handed back)
+    if (W->st != SPIDER_OK) (void)hipStreamSynchronize(S->stream);
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (size_t i = 0; i < W->reqs.size(); ++i) {
+        ServerRequest* r = W->reqs[i];
+        if (r->done) continue;
+        r->planned -= W->adv[i];
+        r->remaining -= W->adv[i];
+        if (W->st != SPIDER_OK)
+          finish(S, r, W->st);
+        else if (r->remaining <= 0)
+          finish(S, r, SPIDER_OK);
+      }
+      std::vector<ServerRequest*> still;
+      for (ServerRequest* r : S->active)
+        if (!r->done) still.push_back(r);
+      S->active.swap(still);
+    }
+    if (R.reqs.empty()) {
+      pending = nullptr;
+    } else {
+      pending = &R;
+      next ^= 1;
+    }
   }
+  for (auto& R : rounds) (void)hipEventDestroy(R.done);
 }
 
 }  // namespace
