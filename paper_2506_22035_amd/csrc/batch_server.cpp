@@ -455,7 +455,10 @@ struct ServerRequest {
 struct spider_server_s {
   size_t budget = 0, used = 0;
   int max_slots = 0, max_queue = 0;
-  int round_steps = 8;
+  // steps per request per round (serving mix, pipelined rounds, A/B on one box: 4 / 8 / 16 /
+  // 24 / 32 steps gave 2225 / 2490 / 2560-2618 / 2611-2625 / 2551-2584 requests/s at
+  // saturation; 16 keeps the lower latency at light load)
+  int round_steps = 16;
   int device = 0;
   std::mutex mu;
   std::condition_variable cv;
