@@ -758,8 +758,9 @@ def main():
             out["ablation_gstencil_s"] = abl
         if headline:
             out["configs"] = other_configs(torch, sp, si, stream, oracle)
-            # a short serving sample (the full sweep is `bench.py --serving`)
-            out["serving_sample"] = serving(torch, sp, si, 200, [0.75])
+            # serving: saturation and two Poisson loads over 1000 requests of the mix
+            # (the four-rate sweep is `bench.py --serving`)
+            out["serving_sample"] = serving(torch, sp, si, 1000, [0.5, 1.0])
 
     if headline and not args.no_cpu_baseline:
         oracle = load_oracle()
