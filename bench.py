@@ -529,7 +529,8 @@ def other_configs(torch, sp, si, stream, oracle):
                  "plain_gpu_fp32": {"value": round(v32, 2), "engine": "direct (VALU fp32)",
                                     "error_vs_fp64_oracle": e32, "hbm_compulsory": run_hbm(i32, wl, "f32")},
                  "f32_carry_sparse_split3": {"value": round(vs3, 2), "time_steps_per_launch": is3["time_block"],
-                                             "error_vs_fp64_oracle": es3, "hbm_compulsory": run_hbm(is3, wl, "f32")},
+                                             "error_vs_fp64_oracle": es3, "hbm_compulsory": run_hbm(is3, wl, "f32"),
+                                             "mfma": run_mfma(is3)},
                  "speedup_f16_over_plain_fp32": round(v16 / v32, 3),
                  "speedup_f32_carry_over_plain_fp32": round(vs3 / v32, 3)}
     # Box-3D27P 512^3 + Heat-3D 256^3 in one batched launch per step
@@ -740,7 +741,7 @@ def main():
             out["f32_carry_sparse_split3"] = {
                 "value": round(vm, 2), "unit": "GStencil/s", "time_steps_per_launch": im["time_block"],
                 "tile_h": im["tile_h2"] or im["tile_h"], "hbm_compulsory": run_hbm(im, wl, "f32"),
-                "error_vs_fp64_oracle": full_grid_error(oracle, wl["coeffs"], x32h, T, gm, "f32s3"),
+                "mfma": run_mfma(im), "error_vs_fp64_oracle": full_grid_error(oracle, wl["coeffs"], x32h, T, gm, "f32s3"),
                 "speedup_over_plain_fp32": round(vm / v32, 3)}
             del gm, x32h
             # ablation: the other engine / operand type on the same pass; bf16 with its error

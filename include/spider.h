@@ -209,9 +209,9 @@ spider_status spider_plan_info(spider_plan_t plan, int* engine, int* carry, int*
  * Either output pointer may be NULL.  With steps == time_block the loop is exactly
  * one launch of the plan's fused kernel.
  * Errors: INVALID (null plan, steps < 0), UNSUPPORTED (matrix_instructions asked
- * for a plan other than paired-line bands with a 16-bit carry, a 1-D line, a 3-D grid
- * at one step per launch with a 16-bit carry, or the direct engine; *launches is
- * still set).
+ * for a plan other than paired-line bands (any carry), a 1-D line, a 3-D grid at
+ * one step per launch with a 16-bit carry, or the direct engine; *launches is still
+ * set).
  */
 spider_status spider_plan_work(spider_plan_t plan, int steps, uint64_t* launches, uint64_t* matrix_instructions);
 

@@ -789,11 +789,11 @@ spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* ti
   return SPIDER_OK;
 }
 
-// Matrix instructions of one launch of a paired-line band kernel with a 16-bit
-// carry advancing T steps on grid `g`: each wave (strip x segment) streams
-// ceil(npin / UP) bodies of UP input line pairs, npin = ceil(rows / 2) + T r + T - 1,
-// and every streamed pair costs T passes x 2 halves x (r + 1) pair instructions
-// (one smfmac, or two dense mfma).
+// Matrix instructions of one launch of a paired-line band kernel advancing T steps
+// on grid `g`: each wave (strip x segment) streams ceil(npin / UP) bodies of UP
+// input line pairs, npin = ceil(rows / 2) + T r + T - 1, and every streamed pair
+// costs T passes x 2 halves x (r + 1) pair instructions (one smfmac, or two dense
+// mfma), twice over for an fp32 carry split into three terms (hi and lo lines).
 static uint64_t pair_launch_instructions(const spider_plan_s* p, const BandGrid& g, int T) {
   const int np = p->r + 1, up = np >= 3 ? np : 2 * np;
   uint64_t iters = 0;
@@ -802,7 +802,8 @@ static uint64_t pair_launch_instructions(const spider_plan_s* p, const BandGrid&
     const int npin = (hrows + 1) / 2 + T * p->r + (T - 1);
     iters += (uint64_t)((npin + up - 1) / up) * up;
   }
-  const uint64_t per_iter = (uint64_t)T * 2 * np * (p->engine == SPIDER_ENGINE_DENSE ? 2 : 1);
+  const int nlp = (p->carry == SPIDER_F32 && p->split == 3) ? 2 : 1;
+  const uint64_t per_iter = (uint64_t)T * 2 * np * nlp * (p->engine == SPIDER_ENGINE_DENSE ? 2 : 1);
   return iters * (uint64_t)g.nstrips * per_iter;
 }
 
@@ -853,12 +854,12 @@ spider_status spider_plan_work(spider_plan_t p, int steps, uint64_t* launches, u
   if (!matrix_instructions) return SPIDER_OK;
   *matrix_instructions = 0;
   if (p->engine == SPIDER_ENGINE_DIRECT || total == 0) return SPIDER_OK;
-  const bool pair16 = p->band_h == 8 && p->carry == p->operand;
+  const bool pair = p->band_h == 8;
   const bool line = p->ndim == 1;
   const bool volume = p->ndim == 3 && p->carry == p->operand && p->time_block == 1;
-  if (!pair16 && !line && !volume)
-    return fail(SPIDER_ERR_UNSUPPORTED, "matrix instruction counts are kept for paired-line bands with a 16-bit "
-                                        "carry, 1-D lines and 3-D grids at one step per launch with a 16-bit carry");
+  if (!pair && !line && !volume)
+    return fail(SPIDER_ERR_UNSUPPORTED, "matrix instruction counts are kept for paired-line bands, 1-D lines and "
+                                        "3-D grids at one step per launch with a 16-bit carry");
   uint64_t n = 0;
   for (int k = 1; k <= total; ++k) {
     const int kind = L.kind(k);

@@ -24,6 +24,10 @@ CASES = [
     ("box3d27p_512", dict(carry="f16", engine="sparse"), 20, False),
     ("heat3d_256", dict(carry="f16", engine="dense"), 20, False),
     ("box2d49p_10240", dict(carry="f16", engine="sparse", time_block=4), 11, True),
+    ("box2d49p_10240", dict(carry="f32", engine="sparse", split=3, time_block=3), 10, True),
+    ("box2d49p_10240", dict(carry="f32", engine="sparse", split=2, time_block=2), 5, True),
+    ("star2d13p_8192", dict(carry="f32", engine="dense", split=3, time_block=1), 3, True),
+    ("box2d49p_10240", dict(carry="f32", engine="sparse", split=3, time_block=3), 3, False),
 ]
 i = int(sys.argv[1])
 name, kw, steps, small = CASES[i]
