@@ -69,28 +69,39 @@ typedef struct {
                       3 = fp32 carry only: also splits every input value x = x_hi + x_lo
                           and adds the products with x_lo (two instructions per kernel row) */
     int tile_h;    /* output rows per wavefront segment, 0 = chosen by the autotuner */
-    int use_graph; /* 1 = capture each (in, out, steps) time loop once as a hipGraph and
-                      replay it (default), 0 = launch every step */
+    int use_graph; /* 1 = capture each (in, out, steps) time loop of two or more launches
+                      once as a hipGraph and replay it (default; a loop of one launch is
+                      launched directly), 0 = launch every step */
     int autotune;  /* 1 = when tile_h is 0, time candidate segment heights on the device at
                       plan time and keep the fastest (results cached per shape, radius,
                       engine and dtype for the life of the process); 0 = occupancy heuristic */
-    int time_block; /* time steps fused per launch: 0 = automatic (paired-line bands with
-                       a 16-bit carry: four from 2^25 points, three from 2^23, else two;
-                       1-D lines with a 16-bit carry and radius <= 3: four from 2^22
-                       points, else two; other 2-D grids of radius <= 3 on the matrix
-                       engines with a 16-bit carry or with paired-line bands: two; else
-                       one; the dense engine fuses at most three),
-                       3-D grids: one (two fused steps, radius 1 with a 16-bit carry, only
-                       when asked for: measured slower on the 512^3 and 256^3 workloads),
-                       1 = one step per launch, 2 = two where supported, 3 or 4 = that many
-                       for paired-line bands with a 16-bit carry and for 1-D lines with
-                       a 16-bit carry and radius <= 3 (else two where supported, else
-                       one).  With 0 and autotune the plan also times the depths and
-                       keeps the fastest per step.  A time loop of n steps runs n / T
-                       fused launches, then (T > 2) one two-step launch for a
-                       remainder of two or three steps, then a single step for one.  The results agree
-                       to rounding; on 1-D lines they are identical bit for bit, and see
-                       band_height for 2-D. */
+    int time_block; /* time steps fused per launch, 0..16 (default 0 = automatic):
+                       - paired-line bands with a 16-bit carry: up to four (the dense
+                         engine three); automatic: four from 2^25 points, three from
+                         2^23, else two;
+                       - paired-line bands with an fp32 carry: up to three on the sparse
+                         engine, two on the dense one; automatic: as above, capped;
+                       - other 2-D grids of radius <= 3 on the matrix engines with a
+                         16-bit carry: two;
+                       - 1-D lines of radius <= 3 (16-bit or fp32 carry): up to four;
+                         automatic: 16-bit four from 2^22 points, else two; fp32 two;
+                       - 3-D grids: two for radius 1 with a 16-bit carry, only when asked
+                         for (measured slower on the 512^3 and 256^3 workloads);
+                       - the direct engine on 2-D grids of radius <= 3: up to 16 steps
+                         in LDS tiles of 32 x 32 outputs with a halo of T r points, at
+                         most 64 points a side (radius 2: 8, radius 3: 5); automatic: the
+                         most it allows on grids of up to 2^20 points (where single-step
+                         launches are bound by latency), else one; bit-identical to
+                         single steps;
+                       - anything else: one.
+                       Larger values are capped at the plan's maximum.  With 0 and
+                       autotune the matrix-engine plans also time the depths and keep
+                       the fastest per step.  A time loop of n steps runs n / T fused
+                       launches, then (T > 2) one two-step launch for a remainder of two
+                       or three steps, then a single step for one; the direct engine
+                       runs its remainder as one launch.  The results agree to rounding;
+                       on 1-D lines and on the direct engine they are identical bit for
+                       bit, and see band_height for 2-D. */
     int operand;   /* matrix engines with an fp32 carry: 16-bit operand type, SPIDER_F16
                       (default, also when 0) or SPIDER_BF16.  With a 16-bit carry the operand
                       is the carry type and this field must be 0 or equal to it. */
@@ -191,7 +202,8 @@ spider_status spider_plan_destroy(spider_plan_t plan);
  *   (kernel rows on the matrix path; for paired-line bands the r + 1 instructions
  *   per input line pair), scratch_bytes (size of the grid-sized scratch buffer the
  *   plan allocates on first use), time_block (steps fused per launch), tile_h2
- *   (segment height of the fused kernel, 0 if time_block is 1), band_height (output
+ *   (segment height of the fused kernel, 0 if time_block is 1 and for the direct
+ *   engine, whose fused kernel uses fixed 32 x 32 tiles), band_height (output
  *   points per band row: 16, or 8 for paired-line bands; 0 for the direct engine).
  *   Any output pointer may be NULL.
  */

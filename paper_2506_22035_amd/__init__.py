@@ -46,6 +46,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise SpiderError(-1, "libspider.so is not built (run python -m paper_2506_22035_amd.build)")
+        # The library must run on the same HIP runtime as torch, whose stream handles and
+        # device pointers it is given.  torch ships its own copy of libamdhip64.so.7;
+        # importing torch first loads it, and the library then binds to it by its soname
+        # (loaded the other way round, the process would hold two runtimes and the
+        # second to initialise would find no GPU).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64
         sig = {

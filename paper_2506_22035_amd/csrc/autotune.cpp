@@ -191,6 +191,8 @@ static hipError_t tune_fused(spider_plan_s* p, void* tmp, hipStream_t s, hipEven
 }
 
 spider_status autotune_tile(spider_plan_s* p) {
+  // the direct engine's multi-step kernel has fixed tiles: nothing to time
+  if (p->engine == SPIDER_ENGINE_DIRECT && p->time_block >= 2) return SPIDER_OK;
   const Key k = key_of(p);
   {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -145,6 +145,18 @@ constexpr int kRowsY3 = 4;
 hipError_t launch_direct(int ndim, int r, int dtype, int zero_taps, const void* in, void* out, int nz, int ny,
                          int nx, const void* coeffs_dev, int seg_h, hipStream_t s);
 
+// The direct engine on 2-D grids with several steps per launch: tiles of 32 x 32
+// outputs advanced `steps` steps in LDS (halo steps x r, radius <= 3), for grids
+// whose single-step launches are bound by latency.  steps in 1 ..
+// direct2d_fused_max_steps (0: no fused kernel for this radius and dtype).
+constexpr int kDirectFusedMaxSteps = 16;
+constexpr int kDirectFusedMaxRadius = 3;
+constexpr size_t kDirectFusedLdsBytes = 65536;
+constexpr long long kDirectFusedMaxPoints = 1LL << 20;  // automatic choice: fused up to this grid size
+int direct2d_fused_max_steps(int r, int dtype);
+hipError_t launch_direct2d_fused(int r, int dtype, int zero_taps, const void* in, void* out, int ny, int nx,
+                                 const void* coeffs_dev, int steps, hipStream_t s);
+
 // Fill n elements of `buf` (dtype: 0 f64, 1 f32, 2 f16, 3 bf16) with pseudo-random
 // values in [0.25, 1) derived from the index and `seed` (the autotuner's timing data).
 hipError_t launch_fill_uniform(void* buf, size_t n, int dtype, uint32_t seed, hipStream_t s);

@@ -307,6 +307,135 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
   }
 }
 
+// ------------------------------------------------------------------ 2-D, several steps per launch
+// Small grids are bound by launch latency, not by HBM: a workgroup loads a
+// kFusedTile^2 output tile with a halo of S r points on every side (W = 32 + 2 S r
+// <= 64 points a side) into LDS once, advances it S steps there (the region still
+// exact after step s shrinks by r per side each step; points outside the grid stay
+// zero), and stores the tile.  In each step a lane owns one column and computes the
+// rows wave, wave + NW, ... of it (NW = 16 waves up to radius 2, 8 at radius 3,
+// whose taps take more registers), every point independently, so the LDS reads of
+// a thread's points overlap: with few tiles per grid the per-step latency, not the
+// arithmetic, sets the time.  Each point sums its taps in the single-step kernel's
+// order (kernel rows, then taps along x, one fused multiply-add each), so the two
+// kernels agree bit for bit.
+constexpr int kFusedTile = 32;
+constexpr int kFusedMaxSide = 64;
+
+template <int R>
+constexpr int fused_waves() {
+  return R <= 2 ? 16 : 8;
+}
+
+template <typename T, int R, int ZM>
+__global__ __launch_bounds__(64 * fused_waves<R>()) void direct2d_fused_kernel(
+    const T* __restrict__ in, T* __restrict__ out, int ny, int nx, const T* __restrict__ w, int S, int ntx) {
+  constexpr int RR = 2 * R + 1;
+  constexpr int NW = fused_waves<R>();
+  extern __shared__ __align__(16) unsigned char fused_lds[];
+  const int H = S * R, W = kFusedTile + 2 * H;
+  T* const lds = reinterpret_cast<T*>(fused_lds);  // two W x W buffers; indexed by offset so
+                                                    // the accesses stay LDS instructions
+  const int gx0 = (int)(blockIdx.x % ntx) * kFusedTile - H, gy0 = (int)(blockIdx.x / ntx) * kFusedTile - H;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T c[RR * RR];
+#pragma unroll
+  for (int i = 0; i < RR * RR; ++i) {
+    c[i] = w[i];
+    // beyond radius 1 the taps outnumber the scalar registers: keep them in vector ones
+    if constexpr (R >= 2) asm volatile("" : "+v"(c[i]));
+  }
+  const int x = gx0 + lane;
+  const bool xin = x >= 0 && x < nx;
+  {
+    // every load of the tile issued before the first LDS write (rows wave, wave + NW, ...)
+    constexpr int kRowsPerWave = kFusedMaxSide / NW;
+    T ld[kRowsPerWave];
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int ly = wave + NW * k, y = gy0 + ly;
+      ld[k] = (lane < W && ly < W && xin && y >= 0 && y < ny) ? in[(size_t)y * nx + x] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const int ly = wave + NW * k;
+      if (lane < W && ly < W) lds[ly * W + lane] = ld[k];
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s <= S; ++s) {
+    const T* src = lds + ((s - 1) & 1) * W * W;
+    T* dst = lds + (s & 1) * W * W;
+    const int lo = s * R, hi = W - s * R;  // rows and columns [lo, hi) are exact after step s
+    // a lane computes column `lane`; LDS reads are issued unconditionally (at
+    // clamped, valid positions) so that they overlap, and only the writes are
+    // predicated
+    const int lx = min(max(lane, lo), hi - 1);
+    constexpr int KR = kFusedMaxSide / NW;
+    if constexpr (R == 1) {
+      // radius 1: a wave owns KR consecutive rows and reads the KR + 2 input rows
+      // they need once (3 values per row per lane), all before the first product
+      const int ly0 = lo + KR * wave;
+      T v[KR + 2][3];
+#pragma unroll
+      for (int j = 0; j < KR + 2; ++j) {
+        const T* p = src + min(ly0 - 1 + j, hi) * W + (lx - 1);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) v[j][t] = p[t];
+      }
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            if (ZM == 2 && a != 1 && t != 1) continue;
+            const T cc = c[a * 3 + t];
+            if (ZM != 1 || cc != T(0)) acc = fma_t<T>(cc, v[k + a][t], acc);
+          }
+        }
+        const int ly = ly0 + k;
+        if (ly < hi && lane >= lo && lane < hi) {
+          const int y = gy0 + ly;
+          const bool inside = xin && y >= 0 && y < ny;
+          if (s < S)
+            dst[ly * W + lane] = inside ? acc : T(0);
+          else if (inside)
+            out[(size_t)y * nx + x] = acc;
+        }
+      }
+    } else {
+      // wider stencils: rows lo + wave + NW k, one point at a time (their reads
+      // alone fill the registers)
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int ly = lo + wave + NW * k;
+        const T* p = src + (min(ly, hi - 1) - R) * W + (lx - R);
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < RR; ++a) {
+#pragma unroll
+          for (int t = 0; t < RR; ++t) {
+            if (ZM == 2 && a != R && t != R) continue;
+            const T cc = c[a * RR + t];
+            if (ZM != 1 || cc != T(0)) acc = fma_t<T>(cc, p[a * W + t], acc);
+          }
+        }
+        if (ly < hi && lane >= lo && lane < hi) {
+          const int y = gy0 + ly;
+          const bool inside = xin && y >= 0 && y < ny;
+          if (s < S)
+            dst[ly * W + lane] = inside ? acc : T(0);
+          else if (inside)
+            out[(size_t)y * nx + x] = acc;
+        }
+      }
+    }
+    if (s < S) __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ dispatch
 
 // 1-D: each lane computes 4 consecutive points; the 4 + 2R inputs it needs are
@@ -393,6 +522,68 @@ static hipError_t direct_zm(int zmode, int ndim, int r, const void* in, void* ou
     case 2: return direct_dispatch<T, 2>(ndim, r, in, out, nz, ny, nx, w, seg_h, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// LDS bytes of the fused 2-D kernel at S steps per launch.
+static size_t direct2d_fused_lds(int r, int elem, int S) {
+  const size_t W = (size_t)kFusedTile + 2 * (size_t)S * r;
+  return 2 * W * W * (size_t)elem;
+}
+
+int direct2d_fused_max_steps(int r, int dtype) {
+  if (r < 1 || r > kDirectFusedMaxRadius || (dtype != 0 && dtype != 1)) return 0;
+  const int elem = dtype == 0 ? 8 : 4;
+  int S = 0;
+  while (S < kDirectFusedMaxSteps && kFusedTile + 2 * (S + 1) * r <= kFusedMaxSide &&
+         direct2d_fused_lds(r, elem, S + 1) <= kDirectFusedLdsBytes)
+    ++S;
+  return S;
+}
+
+template <typename T, int ZM>
+static hipError_t direct2d_fused_zm(int r, const void* in, void* out, int ny, int nx, const void* w, int S,
+                                    hipStream_t s) {
+  const int ntx = (nx + kFusedTile - 1) / kFusedTile, nty = (ny + kFusedTile - 1) / kFusedTile;
+  const size_t lds = direct2d_fused_lds(r, (int)sizeof(T), S);
+  const dim3 grid(ntx * nty);
+  const T* pin = static_cast<const T*>(in);
+  T* pout = static_cast<T*>(out);
+  const T* pw = static_cast<const T*>(w);
+  switch (r) {
+#define SPIDER_DF(RV)                                                                                          \
+  case RV:                                                                                                     \
+    hipLaunchKernelGGL((direct2d_fused_kernel<T, RV, ZM>), grid, dim3(64 * fused_waves<RV>()), lds, s, pin, pout, \
+                       ny, nx, pw, S, ntx);                                                                    \
+    break;
+    SPIDER_DF(1) SPIDER_DF(2) SPIDER_DF(3)
+#undef SPIDER_DF
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_direct2d_fused(int r, int dtype, int zero_taps, const void* in, void* out, int ny, int nx,
+                                 const void* coeffs_dev, int steps, hipStream_t s) {
+  if (steps < 1 || steps > direct2d_fused_max_steps(r, dtype) || ny < 1 || nx < 1) return hipErrorInvalidValue;
+  if ((long long)((ny + kFusedTile - 1) / kFusedTile) * ((nx + kFusedTile - 1) / kFusedTile) > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+  if (dtype == 0) {
+    switch (zero_taps) {
+      case 0: return direct2d_fused_zm<double, 0>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      case 1: return direct2d_fused_zm<double, 1>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      case 2: return direct2d_fused_zm<double, 2>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (dtype == 1) {
+    switch (zero_taps) {
+      case 0: return direct2d_fused_zm<float, 0>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      case 1: return direct2d_fused_zm<float, 1>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      case 2: return direct2d_fused_zm<float, 2>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_direct(int ndim, int r, int dtype, int zero_taps, const void* in, void* out, int nz, int ny,

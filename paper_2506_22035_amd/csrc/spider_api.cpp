@@ -180,7 +180,16 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
   return SPIDER_OK;
 }
 
+// `steps` steps of a direct-engine plan on a 2-D grid in one launch (LDS tiles).
+static spider_status launch_direct_steps(spider_plan_s* p, const void* src, void* dst, int steps, hipStream_t s) {
+  const hipError_t e = launch_direct2d_fused(p->r, p->carry == SPIDER_F64 ? 0 : 1, p->star ? 2 : (p->has_zero_tap ? 1 : 0),
+                                             src, dst, p->ny, p->nx, p->d_coeffs, steps, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return SPIDER_OK;
+}
+
 spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
+  if (p->engine == SPIDER_ENGINE_DIRECT) return launch_direct_steps(p, src, dst, p->time_block, s);
   BandGrid g = p->grid_tb2;
   g.in = src;
   g.out = dst;
@@ -341,11 +350,14 @@ static spider_status launch_rem2(spider_plan_s* p, const void* src, void* dst, h
 // > 2) two-step launches for a remainder of two or three steps, then single steps:
 // buffers b_0 = in, b_1 .. b_L (L launches) with b_L = out, alternating between out
 // and the plan's scratch so that the last launch lands in out and `in` is never
-// written (unless in == out).
+// written (unless in == out).  The direct engine's fused kernel takes any step
+// count, so its remainder is one launch of `rem` steps (in the place of the
+// two-step launches).
 struct LoopShape {
-  int fused;  // launches of time_block steps: k = 1 .. fused
-  int two;    // then two-step launches: k = fused + 1 .. fused + two
-  int total;  // then single steps up to k = total
+  int fused;    // launches of time_block steps: k = 1 .. fused
+  int two;      // then two-step launches (direct engine: one launch of rem steps)
+  int total;    // then single steps up to k = total
+  int rem = 0;  // direct engine: steps of the remainder launch
   int kind(int k) const { return k <= fused ? 3 : (k <= fused + two ? 2 : 1); }
   int run_end(int k) const { return k <= fused ? fused : (k <= fused + two ? fused + two : total); }
 };
@@ -353,6 +365,13 @@ struct LoopShape {
 static LoopShape loop_launches(const spider_plan_s* p, int steps) {
   LoopShape L;
   const int tb = p->time_block;
+  if (p->engine == SPIDER_ENGINE_DIRECT && tb >= 2) {
+    L.fused = steps / tb;
+    L.rem = steps - tb * L.fused;
+    L.two = L.rem > 0 ? 1 : 0;
+    L.total = L.fused + L.two;
+    return L;
+  }
   L.fused = tb >= 2 ? steps / tb : 0;
   const int rem = steps - (tb >= 2 ? tb * L.fused : 0);
   L.two = tb > 2 ? rem / 2 : 0;
@@ -369,7 +388,8 @@ static spider_status enqueue_launches(spider_plan_s* p, const void* src, void* o
     if (dst == src) return fail(SPIDER_ERR_INVALID, "internal: launch %d reads and writes one buffer", k);
     const int kind = L.kind(k);
     spider_status st = kind == 3   ? launch_step2(p, src, dst, s)
-                       : kind == 2 ? launch_rem2(p, src, dst, s)
+                       : kind == 2 ? (p->engine == SPIDER_ENGINE_DIRECT ? launch_direct_steps(p, src, dst, L.rem, s)
+                                                                        : launch_rem2(p, src, dst, s))
                                    : launch_step(p, src, dst, s);
     if (st != SPIDER_OK) return st;
     src = dst;
@@ -544,7 +564,8 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
   if (matrix && ndim == 3 && radius > 1)
     return fail(SPIDER_ERR_UNSUPPORTED, "matrix engines run 3-D grids with radius 1 only");
   if (o.tile_h < 0) return fail(SPIDER_ERR_INVALID, "tile_h must be >= 0");
-  if (o.time_block < 0 || o.time_block > 4) return fail(SPIDER_ERR_INVALID, "time_block must be 0..4");
+  if (o.time_block < 0 || o.time_block > kDirectFusedMaxSteps)
+    return fail(SPIDER_ERR_INVALID, "time_block must be 0..%d", kDirectFusedMaxSteps);
   if (o.band_height != 0 && o.band_height != 8 && o.band_height != 16)
     return fail(SPIDER_ERR_INVALID, "band_height must be 0, 8 or 16");
   if (o.band_height == 8 && !(matrix && ndim == 2 && radius <= 3 && shape[1] < (1LL << 28)))
@@ -612,6 +633,14 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       if (off > 1 && p->coeffs[i] != 0.0) p->star = false;
     }
     p->tile_h = o.tile_h ? o.tile_h : auto_tile_h_direct(p);
+    // 2-D grids: several steps per launch in LDS tiles where single-step launches
+    // are bound by latency (grids of up to 2^20 points: measured faster there for
+    // radius 1 to 3 in fp32 and fp64, slower from 2048^2), or when asked for
+    const int maxT = ndim == 2 ? direct2d_fused_max_steps(radius, p->carry == SPIDER_F64 ? 0 : 1) : 1;
+    p->max_time_block = maxT >= 2 ? maxT : 1;
+    const long long pts2 = (long long)p->ny * p->nx;
+    const int Td = o.time_block ? o.time_block : (pts2 <= kDirectFusedMaxPoints ? p->max_time_block : 1);
+    p->time_block = std::max(1, std::min(Td, p->max_time_block));
   } else {
     // Offline transformation, one kernel row (line of taps along x) at a time, or
     // (paired-line bands) one instruction of r + 1 per input line pair.
@@ -729,8 +758,9 @@ spider_status spider_apply(spider_plan_t p, const void* in, void* out, int steps
     spider_status st = ensure_scratch(p);
     if (st != SPIDER_OK) return st;
   }
-  if (!p->use_graph || steps < 2) return enqueue_steps(p, in, out, steps, s);
   const LoopShape L = loop_launches(p, steps);
+  // a loop of one launch gains nothing from a graph but the graph's own launch cost
+  if (!p->use_graph || steps < 2 || L.total < 2) return enqueue_steps(p, in, out, steps, s);
   if (L.total > 2 * kGraphBody) return enqueue_long(p, in, out, L, s);
   // Replay a graph of the whole time loop, captured once per (in, out, steps).
   auto key = std::make_tuple(in, (const void*)out, steps);
@@ -784,8 +814,8 @@ spider_status spider_plan_info(spider_plan_t p, int* engine, int* carry, int* ti
     *nrows_nonzero = n;
   }
   if (scratch_bytes) *scratch_bytes = p->grid_bytes;
-  if (time_block) *time_block = p->engine == SPIDER_ENGINE_DIRECT ? 1 : p->time_block;
-  if (tile_h2) *tile_h2 = p->time_block >= 2 ? p->tile_h2 : 0;
+  if (time_block) *time_block = p->time_block;
+  if (tile_h2) *tile_h2 = p->time_block >= 2 && p->engine != SPIDER_ENGINE_DIRECT ? p->tile_h2 : 0;
   return SPIDER_OK;
 }
 
@@ -849,7 +879,7 @@ spider_status spider_plan_work(spider_plan_t p, int steps, uint64_t* launches, u
   if (!p) return fail(SPIDER_ERR_INVALID, "plan is NULL");
   if (steps < 0) return fail(SPIDER_ERR_INVALID, "steps must be >= 0");
   const LoopShape L = loop_launches(p, steps);
-  const int total = steps == 0 ? 0 : (p->engine == SPIDER_ENGINE_DIRECT ? steps : L.total);
+  const int total = steps == 0 ? 0 : L.total;
   if (launches) *launches = (uint64_t)total;
   if (!matrix_instructions) return SPIDER_OK;
   *matrix_instructions = 0;

@@ -87,3 +87,18 @@ def test_server_close_releases_tickets_in_flight(monkeypatch):
     srv.close()
     gc.collect()
     assert ref() is None
+
+
+def test_library_shares_torchs_hip_runtime():
+    # Loaded before torch is imported, the library would bring its own HIP runtime and
+    # torch a second one (torch's stream handles would then be foreign to the library,
+    # and the runtime initialised second finds no GPU).  The binding imports torch
+    # first, so one copy of libamdhip64 is mapped whatever the caller imports first.
+    import subprocess
+    import sys
+    code = ("import paper_2506_22035_amd as sp; sp.lib(); import torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=sp.__path__[0] + "/..")
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"

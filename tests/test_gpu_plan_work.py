@@ -78,11 +78,15 @@ def test_sparse_engine_halves_the_dense_instruction_count():
 
 def test_direct_engine_issues_no_matrix_instructions():
     wl = si.workload("box2d9p_256_f64")
-    p = sp.Plan(wl["coeffs"], wl["shape"], carry="f64", engine="direct", use_graph=False)
+    p1 = sp.Plan(wl["coeffs"], wl["shape"], carry="f64", engine="direct", time_block=1, use_graph=False)
+    pf = sp.Plan(wl["coeffs"], wl["shape"], carry="f64", engine="direct", use_graph=False)
     try:
-        assert p.work(7) == (7, 0)
+        assert p1.work(7) == (7, 0)
+        # the small grid runs its steps in LDS tiles, sixteen per launch
+        assert pf.info()["time_block"] == 16 and pf.work(7) == (1, 0) and pf.work(33) == (3, 0)
     finally:
-        p.close()
+        p1.close()
+        pf.close()
 
 
 def test_uncounted_plans_report_no_count_but_their_launches():

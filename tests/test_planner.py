@@ -382,7 +382,7 @@ def test_invalid_arguments_rejected_without_gpu():
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 2
     o = opts(row_swap=2)
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
-    for tb in (-1, 5):
+    for tb in (-1, 17):
         o = opts(time_block=tb)
         assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
     # the explicit row swap: sparse engine, 16-bit carry, 2-D, band height 16, one step per launch
