@@ -212,7 +212,7 @@ def matrix_ceiling(sp, engine, stream, waves=(2, 4), iterations=200000):
 def kernel_name(info, shape, carry, engine, r, row_swap):
     tb = info["time_block"]
     if engine == "direct":
-        kname = "direct%dd_kernel" % len(shape)
+        kname = "direct2d_fused_kernel" if (len(shape) == 2 and tb > 1) else "direct%dd_kernel" % len(shape)
     elif carry == "f32":
         kname = ("band2d_pair_f32_kernel" if info["band_height"] == 8 else "band2d_f32_kernel")
     elif len(shape) == 1:
@@ -583,7 +583,7 @@ def main():
     ap.add_argument("--tile-h", type=int, default=0)
     ap.add_argument("--band-height", type=int, default=0, choices=[0, 8, 16],
                     help="output points per band row (0: the library's choice)")
-    ap.add_argument("--time-block", type=int, default=0, choices=[0, 1, 2, 3, 4],
+    ap.add_argument("--time-block", type=int, default=0, choices=list(range(17)),
                     help="time steps fused per launch (0: the library's choice)")
     ap.add_argument("--row-swap", default="implicit", choices=["implicit", "explicit"],
                     help="row swap in the gather offsets (implicit) or by an LDS copy (explicit; the comparison "
