@@ -163,3 +163,24 @@ def test_batch_and_server_run_fused_direct_plans_alone():
     srv.close()
     for o, w_ in zip(outs2, want):
         assert torch.equal(o, w_)
+
+
+def test_long_loops_of_fused_direct_launches():
+    # more than 512 launches: cached body graphs of 256 fused launches, then the
+    # remainder launch; the same bits as launches without graphs and as single steps
+    rng = np.random.default_rng(5)
+    w = rng.uniform(0, 1, (3, 3))
+    w /= w.sum()
+    shape = (40, 70)
+    xd, _ = to_dev(rng.uniform(0, 1, shape), "f64")
+    pg = sp.Plan(w, shape, carry="f64", engine="direct")
+    pe = sp.Plan(w, shape, carry="f64", engine="direct", use_graph=False)
+    p1 = sp.Plan(w, shape, carry="f64", engine="direct", time_block=1, use_graph=False)
+    T = pg.info()["time_block"]
+    steps = 513 * T + 5
+    assert pg.work(steps)[0] == 514
+    ref = _apply(p1, xd, steps)
+    assert torch.equal(_apply(pe, xd, steps), ref)
+    for _ in range(2):  # the second call replays the cached bodies
+        assert torch.equal(_apply(pg, xd, steps), ref)
+    assert torch.equal(_apply(pg, xd, steps, alias=True), ref)
