@@ -455,7 +455,7 @@ struct ServerRequest {
 struct spider_server_s {
   size_t budget = 0, used = 0;
   int max_slots = 0, max_queue = 0;
-  // steps per request per round (serving mix, pipelined rounds, A/B on one box: 4 / 8 / 16 /
+  // steps per request per round (serving mix, pipelined rounds, A/B on one GPU: 4 / 8 / 16 /
   // 24 / 32 steps gave 2225 / 2490 / 2560-2618 / 2611-2625 / 2551-2584 requests/s at
   // saturation; 16 keeps the lower latency at light load)
   int round_steps = 16;
