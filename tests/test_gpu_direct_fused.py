@@ -184,3 +184,36 @@ def test_long_loops_of_fused_direct_launches():
     for _ in range(2):  # the second call replays the cached bodies
         assert torch.equal(_apply(pg, xd, steps), ref)
     assert torch.equal(_apply(pg, xd, steps, alias=True), ref)
+
+
+def test_random_sweep_of_depths_shapes_and_taps(oracle_mod):
+    # seeded: radius 1..4, ragged grids up to 400 x 400, fp32 / fp64, depth 0..16,
+    # 0..39 steps, graphs on or off, in place or not; integer taps (three of +-1) and
+    # inputs in {-2..2} keep every value an exact integer, so results equal the
+    # oracle bit for bit (radius 4 has no fused kernel and runs single steps)
+    import test_gpu_random_sweep as sweep
+    rng = np.random.default_rng(2507)
+    ran = 0
+    for case in range(300):
+        r = int(rng.integers(1, 5))
+        shape = (int(rng.integers(1, 400)), int(rng.integers(1, 400)))
+        carry = str(rng.choice(["f32", "f64"]))
+        opts = dict(carry=carry, engine="direct", time_block=int(rng.integers(0, 17)),
+                    use_graph=bool(rng.integers(0, 2)))
+        steps = int(rng.integers(0, 40))
+        in_place = bool(rng.integers(0, 2))
+        w = sweep.int_taps(2, r, rng)
+        x = si.grid_integer(shape, -2, 2, 5000 + case)
+        ref, peak = x.astype(np.float64), 2.0
+        for _ in range(steps):
+            ref = oracle_mod.apply(w, ref, 1)
+            peak = max(peak, float(np.abs(ref).max(initial=0)))
+        if peak >= (2.0 ** 24 if carry == "f32" else 2.0 ** 53):
+            continue
+        p = sp.Plan(w, shape, **opts)
+        xd = torch.from_numpy(x).to("cuda:0").to(torch.float32 if carry == "f32" else torch.float64)
+        got = from_dev(_apply(p, xd, steps, alias=in_place))
+        p.close()
+        assert np.array_equal(got, ref), (case, r, shape, opts, steps, in_place)
+        ran += 1
+    assert ran >= 150
