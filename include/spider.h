@@ -84,7 +84,7 @@ typedef struct {
                        - other 2-D grids of radius <= 3 on the matrix engines with a
                          16-bit carry: two;
                        - 1-D lines of radius <= 3 (16-bit or fp32 carry): up to four;
-                         automatic: 16-bit four from 2^22 points, else two; fp32 two;
+                         automatic: four from 2^22 points, else two;
                        - 3-D grids: two for radius 1 with a 16-bit carry, only when asked
                          for (measured slower on the 512^3 and 256^3 workloads);
                        - the direct engine on 2-D grids of radius <= 3: up to 16 steps

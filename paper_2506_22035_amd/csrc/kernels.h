@@ -92,6 +92,9 @@ hipError_t launch_band1d_f32(int r, int operand, int engine, bool xlo, const Ban
 // T = 2..4 fp32-carry steps per launch on a 1-D line (r <= 3); grid as for
 // launch_band1d_tbt (seg_h output blocks per wave)
 hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s);
+// Resident waves per CU of the fused 1-D kernels (aligned: nx % 4 == 0 for fp32, % 8 for 16-bit).
+int band1d_f32_tbt_blocks_per_cu(int r, int operand, int engine, bool xlo, bool aligned, int T);
+int band1d_tbt_blocks_per_cu(int r, int operand, int engine, bool aligned, int T);
 // 3-D (radius 1) band engine on fp32 grids: the 16-bit 3-D decomposition (strips of
 // 256 points, kRowsY3 lines per plane block, seg_h planes per wave) with 16-bit
 // operands split from the fp32 values (x_hi, and x_lo when `xlo`), fp32 stores.

@@ -450,6 +450,30 @@ static hipError_t dispatch1d_tbt_t(int r, int T, const BandGrid& g, hipStream_t 
   return hipErrorInvalidValue;
 }
 
+template <int OP, int ENG, bool AL, int T>
+static int occ1d_tbt(int r) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (r == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_tbt_kernel<1, OP, ENG, AL, T>, 64, 0);
+  if (r == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_tbt_kernel<2, OP, ENG, AL, T>, 64, 0);
+  if (r == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_tbt_kernel<3, OP, ENG, AL, T>, 64, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
+template <int OP, int ENG, bool AL>
+static int occ1d_tbt_t(int r, int T) {
+  return T == 2 ? occ1d_tbt<OP, ENG, AL, 2>(r) : T == 3 ? occ1d_tbt<OP, ENG, AL, 3>(r)
+                                                 : T == 4 ? occ1d_tbt<OP, ENG, AL, 4>(r) : 0;
+}
+
+int band1d_tbt_blocks_per_cu(int r, int operand, int engine, bool aligned, int T) {
+  if (operand == 2 && engine == 1) return aligned ? occ1d_tbt_t<2, 1, true>(r, T) : occ1d_tbt_t<2, 1, false>(r, T);
+  if (operand == 2 && engine == 2) return aligned ? occ1d_tbt_t<2, 2, true>(r, T) : occ1d_tbt_t<2, 2, false>(r, T);
+  if (operand == 3 && engine == 1) return aligned ? occ1d_tbt_t<3, 1, true>(r, T) : occ1d_tbt_t<3, 1, false>(r, T);
+  if (operand == 3 && engine == 2) return aligned ? occ1d_tbt_t<3, 2, true>(r, T) : occ1d_tbt_t<3, 2, false>(r, T);
+  return 0;
+}
+
 hipError_t launch_band1d_tbt(int r, int operand, int engine, int T, const BandGrid& g, hipStream_t s) {
   const bool al = (g.nx % 8) == 0;
   if (operand == 2 && engine == 1) return al ? dispatch1d_tbt_t<2, 1, true>(r, T, g, s) : dispatch1d_tbt_t<2, 1, false>(r, T, g, s);

@@ -769,6 +769,37 @@ hipError_t dispatch1d_f32_tbt_al(int r, bool xlo, int T, const BandGrid& g, hipS
 }
 }  // namespace
 
+namespace {
+template <int OP, int ENG, bool AL, bool XLO, int T>
+int occ1d_f32_tbt(int r) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (r == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<1, OP, ENG, AL, XLO, T>, 64, 0);
+  if (r == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<2, OP, ENG, AL, XLO, T>, 64, 0);
+  if (r == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<3, OP, ENG, AL, XLO, T>, 64, 0);
+  return e == hipSuccess ? nb : 0;
+}
+template <int OP, int ENG, bool AL, bool XLO>
+int occ1d_f32_tbt_t(int r, int T) {
+  return T == 2 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 2>(r)
+         : T == 3 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 3>(r)
+         : T == 4 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 4>(r) : 0;
+}
+template <int OP, int ENG>
+int occ1d_f32_tbt_al(int r, bool xlo, bool al, int T) {
+  if (al) return xlo ? occ1d_f32_tbt_t<OP, ENG, true, true>(r, T) : occ1d_f32_tbt_t<OP, ENG, true, false>(r, T);
+  return xlo ? occ1d_f32_tbt_t<OP, ENG, false, true>(r, T) : occ1d_f32_tbt_t<OP, ENG, false, false>(r, T);
+}
+}  // namespace
+
+int band1d_f32_tbt_blocks_per_cu(int r, int operand, int engine, bool xlo, bool aligned, int T) {
+  if (operand == 2 && engine == 1) return occ1d_f32_tbt_al<2, 1>(r, xlo, aligned, T);
+  if (operand == 2 && engine == 2) return occ1d_f32_tbt_al<2, 2>(r, xlo, aligned, T);
+  if (operand == 3 && engine == 1) return occ1d_f32_tbt_al<3, 1>(r, xlo, aligned, T);
+  if (operand == 3 && engine == 2) return occ1d_f32_tbt_al<3, 2>(r, xlo, aligned, T);
+  return 0;
+}
+
 hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s) {
   if (operand == 2 && engine == 1) return dispatch1d_f32_tbt_al<2, 1>(r, xlo, T, g, s);
   if (operand == 2 && engine == 2) return dispatch1d_f32_tbt_al<2, 2>(r, xlo, T, g, s);

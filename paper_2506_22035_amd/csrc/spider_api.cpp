@@ -274,10 +274,24 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
   }
   if (p->ndim == 1) {
-    // at least 16 output blocks per wave (each wave also computes 2 (T - 1) extra
-    // blocks), and up to about 12 waves per CU
+    // at least 16 output blocks per wave (each wave also reads 2 (T - 1) halo
+    // blocks), and no more waves than the fused kernel keeps resident: a second
+    // generation of waves costs a whole wave's time (1-D fp32 carry, 10^7 points,
+    // three or four steps: 1207-1225 GStencil/s in one generation against 851-934
+    // at 16 blocks per wave)
     const long long nblk = p->grid_template.nstrips;
-    const long long h = (nblk + 12LL * ncu - 1) / (12LL * ncu);
+    int per_cu = p->carry == SPIDER_F32
+                     ? band1d_f32_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, p->nx % 4 == 0,
+                                                    p->time_block)
+                     : band1d_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0, p->time_block);
+    if (per_cu <= 0) per_cu = 8;
+    // beyond two waves per SIMD, a CU share that is not a multiple of its four SIMDs
+    // leaves some SIMD one wave heavier than the others, and that SIMD sets the
+    // launch time (fp32 carry, three steps: 9 waves per CU 1076-1111 GStencil/s,
+    // 8 waves per CU 1207)
+    if (per_cu >= 8) per_cu -= per_cu % 4;
+    const long long slots = (long long)ncu * per_cu;
+    const long long h = (nblk + slots - 1) / slots;
     return (int)std::min<long long>(std::max<long long>(h, 16), nblk);
   }
   if (p->ndim == 3) {
@@ -722,9 +736,11 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
       // deeper fusion pays on large grids; small ones lack waves to hide its longer pipeline
       const long long pts = (long long)p->ny * p->nx;
       // 3-D grids run one step per launch unless two are asked for (time_block = 2)
-      // 1-D lines with an fp32 carry: two (measured fastest on 10^7-point lines)
+      // 1-D lines, 16-bit or fp32 carry: four from 2^22 points (fp32 carry on 10^7
+      // points, one generation of waves: 1225 GStencil/s at four, 1207 at three,
+      // 1003 at two)
       T = ndim == 3   ? 1
-          : ndim == 1 ? (o.carry == SPIDER_F32 ? 2 : pts >= (1LL << 22) ? 4 : 2)
+          : ndim == 1 ? (pts >= (1LL << 22) ? 4 : 2)
                       : (pts >= (1LL << 25) ? 4 : pts >= (1LL << 23) ? 3 : 2);
       p->tune_depth = o.autotune && o.tile_h == 0 && p->max_time_block > 2;
     } else {

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 COUNTED = [
     ("1d3p_10240000", False, dict(carry="f16", engine="sparse", time_block=3), 100, 34, 6004800),
     ("1d3p_10240000", False, dict(carry="f32", engine="sparse", split=3, time_block=2), 100, 50, 10000800),
-    ("1d5p_10240000", False, dict(carry="f32", engine="dense", split=3, time_block=4), 7, 3, 1776256),
+    ("1d5p_10240000", False, dict(carry="f32", engine="dense", split=3, time_block=4), 7, 3, 1546688),
     ("1d5p_10240000", False, dict(carry="f16", engine="dense", time_block=1), 3, 3, 384048),
     ("box3d27p_512", False, dict(carry="f16", engine="sparse"), 20, 20, 98979840),
     ("heat3d_256", False, dict(carry="f16", engine="dense"), 20, 20, 19660800),
