@@ -160,14 +160,19 @@ static std::vector<int> candidates(int h0, int n) {
 
 // Fastest segment height of the fused kernel at the plan's time_block: *h in/out
 // (the starting height), *ms the time of one launch at the chosen height.
+// Launch timings drift with the clock the chip holds, so a candidate replaces the
+// starting height (the occupancy rule's choice) only when it is clearly faster.
+constexpr float kTuneMargin = 0.97f;
+
 static hipError_t tune_fused(spider_plan_s* p, void* tmp, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int* h,
                              float* ms_out) {
-  const int reps = 4;
+  const int reps = 8;
   hipError_t e = hipSuccess;
-  int best = *h;
-  float best_ms = 1e30f;
+  const int h0 = *h;
+  int best = h0;
+  float best_ms = 1e30f, h0_ms = 1e30f;
   const std::vector<int> cand =
-      candidates(*h, p->ndim == 1 ? p->grid_tb2.nstrips : p->ndim == 3 ? p->nz : p->ny);
+      candidates(h0, p->ndim == 1 ? p->grid_tb2.nstrips : p->ndim == 3 ? p->nz : p->ny);
   for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
     set_tile2(p, cand[i]);
     if (launch_step2(p, p->d_scratch, tmp, s) != SPIDER_OK) return hipErrorUnknown;  // warm-up
@@ -179,10 +184,16 @@ static hipError_t tune_fused(spider_plan_s* p, void* tmp, hipStream_t s, hipEven
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && ms < best_ms) {
+    if (e != hipSuccess) break;
+    if (cand[i] == h0) h0_ms = ms;
+    if (ms < best_ms) {
       best_ms = ms;
       best = p->tile_h2;
     }
+  }
+  if (h0_ms < 1e30f && best_ms > kTuneMargin * h0_ms) {
+    best = h0;
+    best_ms = h0_ms;
   }
   *h = best;
   *ms_out = best_ms / reps;
@@ -260,7 +271,7 @@ spider_status autotune_tile(spider_plan_s* p) {
         int h = p->tile_h2;
         float ms = 1e30f;
         e = tune_fused(p, tmp, s, e0, e1, &h, &ms);
-        if (e == hipSuccess && ms / T < best_per_step) {
+        if (e == hipSuccess && ms / T < kTuneMargin * best_per_step) {
           best_per_step = ms / T;
           bestT = T;
           bestT_h = h;

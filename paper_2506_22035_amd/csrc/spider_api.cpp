@@ -311,6 +311,10 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
                : p->time_block > 2 ? band2d_pair_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->time_block)
                                    : band2d_pair_tb2_blocks_per_cu(p->r, p->operand, p->engine);
   if (per_cu <= 0) per_cu = 8;
+  // a third wave per SIMD adds less than the taller segments of two save in halo
+  // rows (two fused steps, paired bands: Box-2D49P 10240^2 1792 GStencil/s at three
+  // waves per SIMD, 2067 at two; Star-2D13P 8192^2 1780 against 2064)
+  per_cu = std::min(per_cu, 8);
   const long long slots = (long long)ncu * per_cu;
   const long long nstrips = p->grid_tb2.nstrips;
   const long long segs = std::max<long long>(1, slots / nstrips);
