@@ -235,9 +235,10 @@ spider_status autotune_tile(spider_plan_s* p) {
   const size_t npts = p->grid_bytes / dtype_bytes(p->carry);
   if (e == hipSuccess) e = launch_fill_uniform(p->d_scratch, npts, p->carry, 0x5eed1u, s);
   if (e == hipSuccess) e = launch_fill_uniform(tmp, npts, p->carry, 0x5eed2u, s);
-  int best = p->tile_h;
-  float best_ms = 1e30f;
-  const int reps = 4;
+  const int h0 = p->tile_h;
+  int best = h0;
+  float best_ms = 1e30f, h0_ms = 1e30f;
+  const int reps = 8;
   for (size_t i = 0; e == hipSuccess && i < cand.size(); ++i) {
     set_tile(p, cand[i]);
     if (launch_step(p, p->d_scratch, tmp, s) != SPIDER_OK) break;  // warm-up
@@ -249,11 +250,14 @@ spider_status autotune_tile(spider_plan_s* p) {
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && ms < best_ms) {
+    if (e != hipSuccess) break;
+    if (p->tile_h == h0) h0_ms = ms;
+    if (ms < best_ms) {
       best_ms = ms;
-      best = cand[i];
+      best = p->tile_h;
     }
   }
+  if (h0_ms < 1e30f && best_ms > kTuneMargin * h0_ms) best = h0;  // keep the rule's height unless clearly beaten
   set_tile(p, best);
   // the fused kernel has its own height, and where the plan lets it, the number
   // of fused steps is chosen too: the fastest time per step over the depths

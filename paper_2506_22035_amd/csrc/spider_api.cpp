@@ -102,6 +102,9 @@ static int auto_tile_h_3d(const spider_plan_s* p) {
                    ? band3d_f32_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, p->rowmask)
                    : band3d_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0, p->rowmask);
   if (per_cu <= 0) per_cu = 8;
+  // at most two waves per SIMD, on taller plane segments (Box-3D27P 512^3, fp16:
+  // 1145 GStencil/s at 43 planes and three waves per SIMD, 1306 at 64 and two)
+  per_cu = std::min(per_cu, 8);
   const long long slots = (long long)ncu * per_cu;
   const long long cols = (long long)((p->nx + kStripW - 1) / kStripW) * ((p->ny + kRowsY3 - 1) / kRowsY3);
   const long long segs = std::max<long long>(1, slots / cols);

@@ -18,7 +18,7 @@ COUNTED = [
     ("1d3p_10240000", False, dict(carry="f32", engine="sparse", split=3, time_block=2), 100, 50, 10000800),
     ("1d5p_10240000", False, dict(carry="f32", engine="dense", split=3, time_block=4), 7, 3, 1546688),
     ("1d5p_10240000", False, dict(carry="f16", engine="dense", time_block=1), 3, 3, 384048),
-    ("box3d27p_512", False, dict(carry="f16", engine="sparse"), 20, 20, 98979840),
+    ("box3d27p_512", False, dict(carry="f16", engine="sparse"), 20, 20, 97320960),
     ("heat3d_256", False, dict(carry="f16", engine="dense"), 20, 20, 19660800),
     ("box2d49p_10240", True, dict(carry="f16", engine="sparse", time_block=4), 11, 4, 76512),
     ("box2d49p_10240", True, dict(carry="f32", engine="sparse", split=3, time_block=3), 10, 4, 128448),
