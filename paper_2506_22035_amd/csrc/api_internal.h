@@ -21,6 +21,7 @@ struct spider_plan_s {
   int band_h = 16;           // output points per band row: 16, or 8 (paired-line bands)
   int row_swap = 0;          // 1: explicit row swap through an LDS copy (ablation)
   int max_time_block = 1;    // deepest fusion this plan supports (paired 16-bit: 4)
+  int direct_tile = 32;      // direct engine, several steps per launch: output tile side (16 or 32)
   bool tune_depth = false;   // the autotuner also chooses time_block (2..max_time_block)
   int tile_h = 0;
   int use_graph = 1;

@@ -157,8 +157,9 @@ constexpr int kDirectFusedMaxRadius = 3;
 constexpr size_t kDirectFusedLdsBytes = 65536;
 constexpr long long kDirectFusedMaxPoints = 1LL << 20;  // automatic choice: fused up to this grid size
 int direct2d_fused_max_steps(int r, int dtype);
+// tile: 32, or 16 (output points per tile side)
 hipError_t launch_direct2d_fused(int r, int dtype, int zero_taps, const void* in, void* out, int ny, int nx,
-                                 const void* coeffs_dev, int steps, hipStream_t s);
+                                 const void* coeffs_dev, int steps, int tile, hipStream_t s);
 
 // Fill n elements of `buf` (dtype: 0 f64, 1 f32, 2 f16, 3 bf16) with pseudo-random
 // values in [0.25, 1) derived from the index and `seed` (the autotuner's timing data).

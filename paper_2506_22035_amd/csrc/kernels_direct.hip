@@ -309,8 +309,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
 
 // ------------------------------------------------------------------ 2-D, several steps per launch
 // Small grids are bound by launch latency, not by HBM: a workgroup loads a
-// kFusedTile^2 output tile with a halo of S r points on every side (W = 32 + 2 S r
-// <= 64 points a side) into LDS once, advances it S steps there (the region still
+// tile^2 output tile (tile = 32, or 16 on grids with fewer 32-point tiles than
+// CUs) with a halo of S r points on every side (W = tile + 2 S r <= 64 points a
+// side) into LDS once, advances it S steps there (the region still
 // exact after step s shrinks by r per side each step; points outside the grid stay
 // zero), and stores the tile.  In each step a lane owns one column and computes the
 // rows wave, wave + NW, ... of it (NW = 16 waves up to radius 2, 8 at radius 3,
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((sizeof(T) =
 // arithmetic, sets the time.  Each point sums its taps in the single-step kernel's
 // order (kernel rows, then taps along x, one fused multiply-add each), so the two
 // kernels agree bit for bit.
-constexpr int kFusedTile = 32;
+constexpr int kFusedTile = 32;  // the largest tile side; the step limit is set for it
 constexpr int kFusedMaxSide = 64;
 
 template <int R>
@@ -329,14 +330,15 @@ constexpr int fused_waves() {
 
 template <typename T, int R, int ZM>
 __global__ __launch_bounds__(64 * fused_waves<R>()) void direct2d_fused_kernel(
-    const T* __restrict__ in, T* __restrict__ out, int ny, int nx, const T* __restrict__ w, int S, int ntx) {
+    const T* __restrict__ in, T* __restrict__ out, int ny, int nx, const T* __restrict__ w, int S, int ntx,
+    int tile) {
   constexpr int RR = 2 * R + 1;
   constexpr int NW = fused_waves<R>();
   extern __shared__ __align__(16) unsigned char fused_lds[];
-  const int H = S * R, W = kFusedTile + 2 * H;
+  const int H = S * R, W = tile + 2 * H;
   T* const lds = reinterpret_cast<T*>(fused_lds);  // two W x W buffers; indexed by offset so
                                                     // the accesses stay LDS instructions
-  const int gx0 = (int)(blockIdx.x % ntx) * kFusedTile - H, gy0 = (int)(blockIdx.x / ntx) * kFusedTile - H;
+  const int gx0 = (int)(blockIdx.x % ntx) * tile - H, gy0 = (int)(blockIdx.x / ntx) * tile - H;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T c[RR * RR];
 #pragma unroll
@@ -525,8 +527,8 @@ static hipError_t direct_zm(int zmode, int ndim, int r, const void* in, void* ou
 }
 
 // LDS bytes of the fused 2-D kernel at S steps per launch.
-static size_t direct2d_fused_lds(int r, int elem, int S) {
-  const size_t W = (size_t)kFusedTile + 2 * (size_t)S * r;
+static size_t direct2d_fused_lds(int r, int elem, int S, int tile = kFusedTile) {
+  const size_t W = (size_t)tile + 2 * (size_t)S * r;
   return 2 * W * W * (size_t)elem;
 }
 
@@ -542,9 +544,9 @@ int direct2d_fused_max_steps(int r, int dtype) {
 
 template <typename T, int ZM>
 static hipError_t direct2d_fused_zm(int r, const void* in, void* out, int ny, int nx, const void* w, int S,
-                                    hipStream_t s) {
-  const int ntx = (nx + kFusedTile - 1) / kFusedTile, nty = (ny + kFusedTile - 1) / kFusedTile;
-  const size_t lds = direct2d_fused_lds(r, (int)sizeof(T), S);
+                                    int tile, hipStream_t s) {
+  const int ntx = (nx + tile - 1) / tile, nty = (ny + tile - 1) / tile;
+  const size_t lds = direct2d_fused_lds(r, (int)sizeof(T), S, tile);
   const dim3 grid(ntx * nty);
   const T* pin = static_cast<const T*>(in);
   T* pout = static_cast<T*>(out);
@@ -553,7 +555,7 @@ static hipError_t direct2d_fused_zm(int r, const void* in, void* out, int ny, in
 #define SPIDER_DF(RV)                                                                                          \
   case RV:                                                                                                     \
     hipLaunchKernelGGL((direct2d_fused_kernel<T, RV, ZM>), grid, dim3(64 * fused_waves<RV>()), lds, s, pin, pout, \
-                       ny, nx, pw, S, ntx);                                                                    \
+                       ny, nx, pw, S, ntx, tile);                                                              \
     break;
     SPIDER_DF(1) SPIDER_DF(2) SPIDER_DF(3)
 #undef SPIDER_DF
@@ -563,23 +565,23 @@ static hipError_t direct2d_fused_zm(int r, const void* in, void* out, int ny, in
 }
 
 hipError_t launch_direct2d_fused(int r, int dtype, int zero_taps, const void* in, void* out, int ny, int nx,
-                                 const void* coeffs_dev, int steps, hipStream_t s) {
+                                 const void* coeffs_dev, int steps, int tile, hipStream_t s) {
   if (steps < 1 || steps > direct2d_fused_max_steps(r, dtype) || ny < 1 || nx < 1) return hipErrorInvalidValue;
-  if ((long long)((ny + kFusedTile - 1) / kFusedTile) * ((nx + kFusedTile - 1) / kFusedTile) > 0x7fffffffLL)
-    return hipErrorInvalidValue;
+  if (tile != 16 && tile != kFusedTile) return hipErrorInvalidValue;
+  if ((long long)((ny + tile - 1) / tile) * ((nx + tile - 1) / tile) > 0x7fffffffLL) return hipErrorInvalidValue;
   if (dtype == 0) {
     switch (zero_taps) {
-      case 0: return direct2d_fused_zm<double, 0>(r, in, out, ny, nx, coeffs_dev, steps, s);
-      case 1: return direct2d_fused_zm<double, 1>(r, in, out, ny, nx, coeffs_dev, steps, s);
-      case 2: return direct2d_fused_zm<double, 2>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      case 0: return direct2d_fused_zm<double, 0>(r, in, out, ny, nx, coeffs_dev, steps, tile, s);
+      case 1: return direct2d_fused_zm<double, 1>(r, in, out, ny, nx, coeffs_dev, steps, tile, s);
+      case 2: return direct2d_fused_zm<double, 2>(r, in, out, ny, nx, coeffs_dev, steps, tile, s);
       default: return hipErrorInvalidValue;
     }
   }
   if (dtype == 1) {
     switch (zero_taps) {
-      case 0: return direct2d_fused_zm<float, 0>(r, in, out, ny, nx, coeffs_dev, steps, s);
-      case 1: return direct2d_fused_zm<float, 1>(r, in, out, ny, nx, coeffs_dev, steps, s);
-      case 2: return direct2d_fused_zm<float, 2>(r, in, out, ny, nx, coeffs_dev, steps, s);
+      case 0: return direct2d_fused_zm<float, 0>(r, in, out, ny, nx, coeffs_dev, steps, tile, s);
+      case 1: return direct2d_fused_zm<float, 1>(r, in, out, ny, nx, coeffs_dev, steps, tile, s);
+      case 2: return direct2d_fused_zm<float, 2>(r, in, out, ny, nx, coeffs_dev, steps, tile, s);
       default: return hipErrorInvalidValue;
     }
   }

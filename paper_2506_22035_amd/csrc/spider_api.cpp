@@ -186,7 +186,7 @@ spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStrea
 // `steps` steps of a direct-engine plan on a 2-D grid in one launch (LDS tiles).
 static spider_status launch_direct_steps(spider_plan_s* p, const void* src, void* dst, int steps, hipStream_t s) {
   const hipError_t e = launch_direct2d_fused(p->r, p->carry == SPIDER_F64 ? 0 : 1, p->star ? 2 : (p->has_zero_tap ? 1 : 0),
-                                             src, dst, p->ny, p->nx, p->d_coeffs, steps, s);
+                                             src, dst, p->ny, p->nx, p->d_coeffs, steps, p->direct_tile, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return SPIDER_OK;
 }
@@ -662,6 +662,15 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
     const long long pts2 = (long long)p->ny * p->nx;
     const int Td = o.time_block ? o.time_block : (pts2 <= kDirectFusedMaxPoints ? p->max_time_block : 1);
     p->time_block = std::max(1, std::min(Td, p->max_time_block));
+    // 16-point tiles where 32-point ones would leave CUs idle (more halo work, but
+    // spread over more CUs: each step's time is one tile's LDS traffic)
+    {
+      int ncu = 256;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) ncu = prop.multiProcessorCount;
+      const long long tiles32 = (long long)((p->ny + 31) / 32) * ((p->nx + 31) / 32);
+      p->direct_tile = tiles32 < ncu ? 16 : 32;
+    }
   } else {
     // Offline transformation, one kernel row (line of taps along x) at a time, or
     // (paired-line bands) one instruction of r + 1 per input line pair.

@@ -1,7 +1,7 @@
 """The direct (vector-ALU) engine with several steps per launch on 2-D grids.
 
-Its multi-step kernel advances 32 x 32 tiles with a halo of T r points T steps in
-LDS.  Every point sums its taps in the single-step kernel's order with the same
+Its multi-step kernel advances 32 x 32 tiles (16 x 16 on grids with fewer 32-point
+tiles than CUs) with a halo of T r points T steps in LDS.  Every point sums its taps in the single-step kernel's order with the same
 fused multiply-adds, so the two must agree bit for bit at any step count (fused
 launches, the remainder launch, aliasing); against the fp64 oracle the results
 meet the stated fp64 / fp32 tolerances, and integer data is exact."""
@@ -45,8 +45,9 @@ def _apply(plan, x, steps, alias=False):
 
 @pytest.mark.parametrize("carry", ["f64", "f32"])
 @pytest.mark.parametrize("kind,r", [("box", 1), ("star", 1), ("holes", 2), ("box", 2), ("box", 3), ("star", 3), ("holes", 3)])
-@pytest.mark.parametrize("shape", [(100, 77), (1, 1), (33, 250), (257, 64), (2, 300)])
+@pytest.mark.parametrize("shape", [(100, 77), (1, 1), (33, 250), (257, 64), (2, 300), (520, 530)])
 def test_fused_equals_single_steps_bit_for_bit(carry, kind, r, shape):
+    # grids of fewer 32-point tiles than CUs run 16-point tiles; (520, 530) runs 32
     rng = np.random.default_rng(r * 1000 + shape[0])
     w = _coeffs(kind, r, rng)
     xd, _ = to_dev(rng.uniform(-1, 1, shape), carry)
