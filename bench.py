@@ -551,13 +551,21 @@ def other_configs(torch, sp, si, stream, oracle):
         vf, iff, gf, xf = workload_run(torch, sp, si, name, "f32", "sparse", 3, 5, stream)
         ef = full_grid_error(oracle, wl["coeffs"], xf, wl["steps"], gf, "f32s3")
         del gf, xf
+        # 16-bit grid, split 3: the levels inside a fused launch kept as hi/lo pairs,
+        # the grid rounded to fp16 once per launch instead of once per step
+        vh, ih, gh, xh = workload_run(torch, sp, si, name, "f16", "sparse", 3, 5, stream)
+        eh = full_grid_error(oracle, wl["coeffs"], xh, wl["steps"], gh, "f16")
+        del gh, xh
         # (the 1-D lines, 20 and 41 MB, stay in the last-level cache between launches)
         modes = {"f16_sparse": {"value": round(v1, 2), "time_steps_per_launch": i1["time_block"],
                                 "tile_h2": i1["tile_h2"], "error_vs_fp64_oracle": e1,
                                 "hbm_compulsory": run_hbm(i1, wl, "f16"), "mfma": run_mfma(i1)},
                  "f32_carry_sparse_split3": {"value": round(vf, 2), "time_steps_per_launch": iff["time_block"],
                                              "tile_h2": iff["tile_h2"], "error_vs_fp64_oracle": ef,
-                                             "hbm_compulsory": run_hbm(iff, wl, "f32"), "mfma": run_mfma(iff)}}
+                                             "hbm_compulsory": run_hbm(iff, wl, "f32"), "mfma": run_mfma(iff)},
+                 "f16_carry_sparse_split3": {"value": round(vh, 2), "time_steps_per_launch": ih["time_block"],
+                                             "tile_h2": ih["tile_h2"], "error_vs_fp64_oracle": eh,
+                                             "hbm_compulsory": run_hbm(ih, wl, "f16"), "mfma": run_mfma(ih)}}
         # the config's value: the fastest mode whose error meets its stated bound
         ok = [(m["value"], k) for k, m in modes.items() if m["error_vs_fp64_oracle"]["pass"]]
         best = max(ok)[1] if ok else None

@@ -66,8 +66,12 @@ typedef struct {
     int split;     /* products on the matrix engines (ignored by the direct engine):
                       1 = w rounded once to the operand type,
                       2 = w_hi + w_lo, each rounded (default),
-                      3 = fp32 carry only: also splits every input value x = x_hi + x_lo
-                          and adds the products with x_lo (two instructions per kernel row) */
+                      3 = fp32 carry: also splits every input value x = x_hi + x_lo
+                          and adds the products with x_lo (two instructions per kernel row);
+                          a 16-bit carry on a 1-D line: the fused launches keep their
+                          intermediate steps as such hi/lo pairs and round the grid to 16
+                          bits once per launch instead of once per step (single-step
+                          launches are those of split 2); other 16-bit grids: INVALID */
     int tile_h;    /* output rows per wavefront segment, 0 = chosen by the autotuner */
     int use_graph; /* 1 = capture each (in, out, steps) time loop of two or more launches
                       once as a hipGraph and replay it (default; a loop of one launch is

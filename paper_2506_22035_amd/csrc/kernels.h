@@ -91,9 +91,12 @@ int band2d_pair_f32_blocks_per_cu(int r, int operand, int engine, bool xlo, int 
 hipError_t launch_band1d_f32(int r, int operand, int engine, bool xlo, const BandGrid& g, hipStream_t s);
 // T = 2..4 fp32-carry steps per launch on a 1-D line (r <= 3); grid as for
 // launch_band1d_tbt (seg_h output blocks per wave)
-hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s);
+// io16: the grid is 16-bit (the operand type) and the levels inside a launch keep
+// their fp32 sums as hi/lo pairs (split 3 with a 16-bit carry)
+hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s,
+                                 bool io16 = false);
 // Resident waves per CU of the fused 1-D kernels (aligned: nx % 4 == 0 for fp32, % 8 for 16-bit).
-int band1d_f32_tbt_blocks_per_cu(int r, int operand, int engine, bool xlo, bool aligned, int T);
+int band1d_f32_tbt_blocks_per_cu(int r, int operand, int engine, bool xlo, bool aligned, int T, bool io16 = false);
 int band1d_tbt_blocks_per_cu(int r, int operand, int engine, bool aligned, int T);
 // 3-D (radius 1) band engine on fp32 grids: the 16-bit 3-D decomposition (strips of
 // 256 points, kRowsY3 lines per plane block, seg_h planes per wave) with 16-bit

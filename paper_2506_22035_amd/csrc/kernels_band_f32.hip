@@ -61,6 +61,29 @@ __device__ __forceinline__ F32Line load_f32_line(__amdgpu_buffer_rsrc_t rs, uint
   return L;
 }
 
+// The same line read from a 16-bit grid (OP's type), widened exactly to fp32.
+template <int OP, bool ALIGNED>
+__device__ __forceinline__ F32Line load_h16_line(__amdgpu_buffer_rsrc_t rs, uint32_t mvoff, uint32_t tvoff) {
+  uint32_t p01, p23;
+  if constexpr (ALIGNED) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(rs, mvoff, 0, 0);
+    p01 = w.x;
+    p23 = w.y;
+  } else {
+    p01 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, mvoff, 0, 0) |
+          ((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, mvoff + 2, 0, 0) << 16);
+    p23 = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, mvoff + 4, 0, 0) |
+          ((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, mvoff + 6, 0, 0) << 16);
+  }
+  const f32x2 a = unpack2<OP>(p01), b = unpack2<OP>(p23);
+  const f32x2 t = unpack2<OP>((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rs, tvoff, 0, 0));
+  F32Line L;
+  L.m = __builtin_bit_cast(u32x4, (f32x4){a.x, a.y, b.x, b.y});
+  L.t = __builtin_bit_cast(uint32_t, t.x);
+  return L;
+}
+
 // Store 4 fp32 outputs; the line resource drops whatever lies outside [0, nx).
 template <bool ALIGNED>
 __device__ __forceinline__ void store_f32x4(__amdgpu_buffer_rsrc_t rs, uint32_t voff, f32x4 v) {
@@ -308,8 +331,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XLO ? 2 : 3)
 // a single fp32-carry step splits its fp32 input after loading it, and zero
 // outside the line; so each output equals that of T single steps bit for bit,
 // while the grid crosses HBM once per launch instead of once per step.
-template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T, bool EDGE>
+// IO16: the grid between launches is 16-bit (OP's type): the input is widened
+// exactly (its lo rows are zero) and only the launch's output is rounded to 16
+// bits, so a fused launch rounds the state once per T steps instead of once per
+// step.
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T, bool EDGE, bool IO16>
 __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, uint32_t* lds) {
+  constexpr int ES = IO16 ? 2 : 4;  // bytes per grid element
   constexpr int U = 4;             // input blocks staged per body (the ring size)
   constexpr int NS = XLO ? 2 : 1;  // LDS rows per level of a block: hi (and lo)
   constexpr int ROWDW = NS * kLdsRowDw;
@@ -328,8 +356,8 @@ __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, ui
   int p1, p2;
   band_gather_offsets(lane, &p1, &p2);
   const __amdgpu_buffer_rsrc_t rin =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * 4, kRsrcWord3);
-  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * 4, kRsrcWord3);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(g.in), (short)0, nx * ES, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(g.out, (short)0, nx * ES, kRsrcWord3);
   // staging: lane l writes row positions 4 l .. 4 l + 3, lanes 0..15 also position 256 + l
   const int mw = lds_phys(2 * lane);
   const int tw_line = lds_phys(128 + (lane >> 1)) * 4 + 2 * (lane & 1);
@@ -346,14 +374,23 @@ __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, ui
   auto load_blk = [&](int it) {  // input block s0 + it, zero where level 1 does not need it
     const int x0 = 256 * (s0 + it) - 8;
     const bool v = it < nin;
-    const uint32_t mvoff = v ? (uint32_t)((x0 - 8 + 4 * lane) * 4) : kOffNone;
-    const uint32_t tvoff = (v && lane < 16) ? (uint32_t)((x0 + 248 + lane) * 4) : kOffNone;
-    return load_f32_line<ALIGNED>(rin, mvoff, tvoff);
+    const uint32_t mvoff = v ? (uint32_t)((x0 - 8 + 4 * lane) * ES) : kOffNone;
+    const uint32_t tvoff = (v && lane < 16) ? (uint32_t)((x0 + 248 + lane) * ES) : kOffNone;
+    if constexpr (IO16)
+      return load_h16_line<OP, ALIGNED>(rin, mvoff, tvoff);
+    else
+      return load_f32_line<ALIGNED>(rin, mvoff, tvoff);
   };
   auto out_off = [&](int it) {  // output block of iteration it
     const int k = s0 + it - 2 * (T - 1);
     const int x = 256 * k + ox;
-    return (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * 4) : kOffNone;
+    return (k >= b0 && k < b0 + nb && x >= 0) ? (uint32_t)(x * ES) : kOffNone;
+  };
+  auto store_blk = [&](uint32_t off, f32x4 v) {
+    if constexpr (IO16)
+      store_packed<ALIGNED>(rout, off, pack_out<OP>(v));
+    else
+      store_f32x4<ALIGNED>(rout, off, v);
   };
   F32Line stg[U];
 #pragma unroll
@@ -380,7 +417,7 @@ __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, ui
     }
     if (jb > 0) {
 #pragma unroll
-      for (int q = 0; q < U; ++q) store_f32x4<ALIGNED>(rout, out_off(jb - U + q), done[q]);
+      for (int q = 0; q < U; ++q) store_blk(out_off(jb - U + q), done[q]);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) stg[q] = load_blk(jb + U + q);
@@ -437,10 +474,10 @@ __device__ __forceinline__ void band1d_f32_tbt_body(const BandGrid& g, int w, ui
     }
   }
 #pragma unroll
-  for (int q = 0; q < U; ++q) store_f32x4<ALIGNED>(rout, out_off(nbody * U - U + q), done[q]);
+  for (int q = 0; q < U; ++q) store_blk(out_off(nbody * U - U + q), done[q]);
 }
 
-template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T>
+template <int R, int OP, int ENG, bool ALIGNED, bool XLO, int T, bool IO16>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void band1d_f32_tbt_kernel(BandGrid g) {
   constexpr int NS = XLO ? 2 : 1;
   __shared__ uint32_t lds[4 * NS * kLdsRowDw + 64 + (T - 1) * 4 * NS * kLdsRowDw];
@@ -450,9 +487,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ba
   const int s0 = w * g.seg_h - (T - 1);
   const int nin = min(g.seg_h, g.nstrips - w * g.seg_h) + 2 * (T - 1);
   if (256 * s0 - 16 >= 0 && 256 * (s0 + nin) + 256 <= g.nx)
-    band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T, false>(g, w, lds);
+    band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T, false, IO16>(g, w, lds);
   else
-    band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T, true>(g, w, lds);
+    band1d_f32_tbt_body<R, OP, ENG, ALIGNED, XLO, T, true, IO16>(g, w, lds);
 }
 
 // ----------------------------------------------------------------------------- 3-D
@@ -740,71 +777,82 @@ hipError_t launch_band1d_f32(int r, int operand, int engine, bool xlo, const Ban
 }
 
 namespace {
-template <int OP, int ENG, bool AL, bool XLO, int T>
+template <int OP, int ENG, bool AL, bool XLO, int T, bool IO16>
 hipError_t dispatch1d_f32_tbt(int r, const BandGrid& g, hipStream_t s) {
   const dim3 grid(g.nblocks), block(64);
   switch (r) {
-    case 1: hipLaunchKernelGGL((band1d_f32_tbt_kernel<1, OP, ENG, AL, XLO, T>), grid, block, 0, s, g); break;
-    case 2: hipLaunchKernelGGL((band1d_f32_tbt_kernel<2, OP, ENG, AL, XLO, T>), grid, block, 0, s, g); break;
-    case 3: hipLaunchKernelGGL((band1d_f32_tbt_kernel<3, OP, ENG, AL, XLO, T>), grid, block, 0, s, g); break;
+    case 1: hipLaunchKernelGGL((band1d_f32_tbt_kernel<1, OP, ENG, AL, XLO, T, IO16>), grid, block, 0, s, g); break;
+    case 2: hipLaunchKernelGGL((band1d_f32_tbt_kernel<2, OP, ENG, AL, XLO, T, IO16>), grid, block, 0, s, g); break;
+    case 3: hipLaunchKernelGGL((band1d_f32_tbt_kernel<3, OP, ENG, AL, XLO, T, IO16>), grid, block, 0, s, g); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
-template <int OP, int ENG, bool AL, bool XLO>
+template <int OP, int ENG, bool AL, bool XLO, bool IO16>
 hipError_t dispatch1d_f32_tbt_t(int r, int T, const BandGrid& g, hipStream_t s) {
-  if (T == 2) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 2>(r, g, s);
-  if (T == 3) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 3>(r, g, s);
-  if (T == 4) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 4>(r, g, s);
+  if (T == 2) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 2, IO16>(r, g, s);
+  if (T == 3) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 3, IO16>(r, g, s);
+  if (T == 4) return dispatch1d_f32_tbt<OP, ENG, AL, XLO, 4, IO16>(r, g, s);
   return hipErrorInvalidValue;
 }
-template <int OP, int ENG>
+template <int OP, int ENG, bool IO16>
 hipError_t dispatch1d_f32_tbt_al(int r, bool xlo, int T, const BandGrid& g, hipStream_t s) {
   const bool al = (g.nx % 4) == 0;
   if (al)
-    return xlo ? dispatch1d_f32_tbt_t<OP, ENG, true, true>(r, T, g, s)
-               : dispatch1d_f32_tbt_t<OP, ENG, true, false>(r, T, g, s);
-  return xlo ? dispatch1d_f32_tbt_t<OP, ENG, false, true>(r, T, g, s)
-             : dispatch1d_f32_tbt_t<OP, ENG, false, false>(r, T, g, s);
+    return xlo ? dispatch1d_f32_tbt_t<OP, ENG, true, true, IO16>(r, T, g, s)
+               : dispatch1d_f32_tbt_t<OP, ENG, true, false, IO16>(r, T, g, s);
+  return xlo ? dispatch1d_f32_tbt_t<OP, ENG, false, true, IO16>(r, T, g, s)
+             : dispatch1d_f32_tbt_t<OP, ENG, false, false, IO16>(r, T, g, s);
 }
-}  // namespace
 
-namespace {
-template <int OP, int ENG, bool AL, bool XLO, int T>
+template <int OP, int ENG, bool AL, bool XLO, int T, bool IO16>
 int occ1d_f32_tbt(int r) {
   int nb = 0;
   hipError_t e = hipErrorInvalidValue;
-  if (r == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<1, OP, ENG, AL, XLO, T>, 64, 0);
-  if (r == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<2, OP, ENG, AL, XLO, T>, 64, 0);
-  if (r == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<3, OP, ENG, AL, XLO, T>, 64, 0);
+  if (r == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<1, OP, ENG, AL, XLO, T, IO16>, 64, 0);
+  if (r == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<2, OP, ENG, AL, XLO, T, IO16>, 64, 0);
+  if (r == 3)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, band1d_f32_tbt_kernel<3, OP, ENG, AL, XLO, T, IO16>, 64, 0);
   return e == hipSuccess ? nb : 0;
 }
-template <int OP, int ENG, bool AL, bool XLO>
+template <int OP, int ENG, bool AL, bool XLO, bool IO16>
 int occ1d_f32_tbt_t(int r, int T) {
-  return T == 2 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 2>(r)
-         : T == 3 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 3>(r)
-         : T == 4 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 4>(r) : 0;
+  return T == 2 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 2, IO16>(r)
+         : T == 3 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 3, IO16>(r)
+         : T == 4 ? occ1d_f32_tbt<OP, ENG, AL, XLO, 4, IO16>(r) : 0;
 }
-template <int OP, int ENG>
+template <int OP, int ENG, bool IO16>
 int occ1d_f32_tbt_al(int r, bool xlo, bool al, int T) {
-  if (al) return xlo ? occ1d_f32_tbt_t<OP, ENG, true, true>(r, T) : occ1d_f32_tbt_t<OP, ENG, true, false>(r, T);
-  return xlo ? occ1d_f32_tbt_t<OP, ENG, false, true>(r, T) : occ1d_f32_tbt_t<OP, ENG, false, false>(r, T);
+  if (al)
+    return xlo ? occ1d_f32_tbt_t<OP, ENG, true, true, IO16>(r, T) : occ1d_f32_tbt_t<OP, ENG, true, false, IO16>(r, T);
+  return xlo ? occ1d_f32_tbt_t<OP, ENG, false, true, IO16>(r, T) : occ1d_f32_tbt_t<OP, ENG, false, false, IO16>(r, T);
 }
 }  // namespace
 
-int band1d_f32_tbt_blocks_per_cu(int r, int operand, int engine, bool xlo, bool aligned, int T) {
-  if (operand == 2 && engine == 1) return occ1d_f32_tbt_al<2, 1>(r, xlo, aligned, T);
-  if (operand == 2 && engine == 2) return occ1d_f32_tbt_al<2, 2>(r, xlo, aligned, T);
-  if (operand == 3 && engine == 1) return occ1d_f32_tbt_al<3, 1>(r, xlo, aligned, T);
-  if (operand == 3 && engine == 2) return occ1d_f32_tbt_al<3, 2>(r, xlo, aligned, T);
+int band1d_f32_tbt_blocks_per_cu(int r, int operand, int engine, bool xlo, bool aligned, int T, bool io16) {
+  if (operand == 2 && engine == 1)
+    return io16 ? occ1d_f32_tbt_al<2, 1, true>(r, xlo, aligned, T) : occ1d_f32_tbt_al<2, 1, false>(r, xlo, aligned, T);
+  if (operand == 2 && engine == 2)
+    return io16 ? occ1d_f32_tbt_al<2, 2, true>(r, xlo, aligned, T) : occ1d_f32_tbt_al<2, 2, false>(r, xlo, aligned, T);
+  if (operand == 3 && engine == 1)
+    return io16 ? occ1d_f32_tbt_al<3, 1, true>(r, xlo, aligned, T) : occ1d_f32_tbt_al<3, 1, false>(r, xlo, aligned, T);
+  if (operand == 3 && engine == 2)
+    return io16 ? occ1d_f32_tbt_al<3, 2, true>(r, xlo, aligned, T) : occ1d_f32_tbt_al<3, 2, false>(r, xlo, aligned, T);
   return 0;
 }
 
-hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s) {
-  if (operand == 2 && engine == 1) return dispatch1d_f32_tbt_al<2, 1>(r, xlo, T, g, s);
-  if (operand == 2 && engine == 2) return dispatch1d_f32_tbt_al<2, 2>(r, xlo, T, g, s);
-  if (operand == 3 && engine == 1) return dispatch1d_f32_tbt_al<3, 1>(r, xlo, T, g, s);
-  if (operand == 3 && engine == 2) return dispatch1d_f32_tbt_al<3, 2>(r, xlo, T, g, s);
+hipError_t launch_band1d_f32_tbt(int r, int operand, int engine, bool xlo, int T, const BandGrid& g, hipStream_t s,
+                                 bool io16) {
+  if (operand == 2 && engine == 1)
+    return io16 ? dispatch1d_f32_tbt_al<2, 1, true>(r, xlo, T, g, s) : dispatch1d_f32_tbt_al<2, 1, false>(r, xlo, T, g, s);
+  if (operand == 2 && engine == 2)
+    return io16 ? dispatch1d_f32_tbt_al<2, 2, true>(r, xlo, T, g, s) : dispatch1d_f32_tbt_al<2, 2, false>(r, xlo, T, g, s);
+  if (operand == 3 && engine == 1)
+    return io16 ? dispatch1d_f32_tbt_al<3, 1, true>(r, xlo, T, g, s) : dispatch1d_f32_tbt_al<3, 1, false>(r, xlo, T, g, s);
+  if (operand == 3 && engine == 2)
+    return io16 ? dispatch1d_f32_tbt_al<3, 2, true>(r, xlo, T, g, s) : dispatch1d_f32_tbt_al<3, 2, false>(r, xlo, T, g, s);
   return hipErrorInvalidValue;
 }
 

@@ -142,6 +142,13 @@ spider_status ensure_scratch(spider_plan_s* p) {
   return SPIDER_OK;
 }
 
+// 1-D lines whose fused launches run the fp32-level kernel: an fp32 carry, or a
+// 16-bit carry with split 3 (the levels inside a launch kept as hi/lo pairs, the
+// grid rounded to 16 bits once per launch).
+static bool line_split_levels(const spider_plan_s* p) {
+  return p->ndim == 1 && (p->carry == SPIDER_F32 || p->split == 3);
+}
+
 // One time step of the plan from `src` to `dst` on `s`.
 spider_status launch_step(spider_plan_s* p, const void* src, void* dst, hipStream_t s) {
   hipError_t e;
@@ -197,8 +204,9 @@ spider_status launch_step2(spider_plan_s* p, const void* src, void* dst, hipStre
   g.in = src;
   g.out = dst;
   hipError_t e =
-      p->ndim == 1   ? (p->carry == SPIDER_F32
-                            ? launch_band1d_f32_tbt(p->r, p->operand, p->engine, p->split == 3, p->time_block, g, s)
+      p->ndim == 1   ? (line_split_levels(p)
+                            ? launch_band1d_f32_tbt(p->r, p->operand, p->engine, p->split == 3, p->time_block, g, s,
+                                                    p->carry != SPIDER_F32)
                             : launch_band1d_tbt(p->r, p->operand, p->engine, p->time_block, g, s))
       : p->ndim == 3 ? launch_band3d_tb2(p->r, p->operand, p->engine, g, s)
       : p->band_h != 8 ? launch_band2d_tb2(p->r, p->operand, p->engine, g, s)
@@ -283,9 +291,9 @@ static int auto_tile_h_tb2(const spider_plan_s* p) {
     // three or four steps: 1207-1225 GStencil/s in one generation against 851-934
     // at 16 blocks per wave)
     const long long nblk = p->grid_template.nstrips;
-    int per_cu = p->carry == SPIDER_F32
+    int per_cu = line_split_levels(p)
                      ? band1d_f32_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->split == 3, p->nx % 4 == 0,
-                                                    p->time_block)
+                                                    p->time_block, p->carry != SPIDER_F32)
                      : band1d_tbt_blocks_per_cu(p->r, p->operand, p->engine, p->nx % 8 == 0, p->time_block);
     if (per_cu <= 0) per_cu = 8;
     // beyond two waves per SIMD, a CU share that is not a multiple of its four SIMDs
@@ -358,8 +366,9 @@ static spider_status launch_rem2(spider_plan_s* p, const void* src, void* dst, h
   g.out = dst;
   // time_block > 2 exists for 1-D lines (16-bit or fp32 carry) and for paired-line
   // bands (16-bit carry, or fp32 carry on the sparse engine)
-  hipError_t e = p->ndim == 1             ? (p->carry == SPIDER_F32
-                                                 ? launch_band1d_f32_tbt(p->r, p->operand, p->engine, p->split == 3, 2, g, s)
+  hipError_t e = p->ndim == 1             ? (line_split_levels(p)
+                                                 ? launch_band1d_f32_tbt(p->r, p->operand, p->engine, p->split == 3, 2, g,
+                                                                         s, p->carry != SPIDER_F32)
                                                  : launch_band1d_tbt(p->r, p->operand, p->engine, 2, g, s))
                  : p->carry == SPIDER_F32 ? launch_band2d_pair_f32(p->r, p->operand, p->engine, p->split == 3, 2, g, s)
                                           : launch_band2d_pair_tb2(p->r, p->operand, p->engine, g, s);
@@ -578,8 +587,9 @@ spider_status spider_plan(const double* coeffs, int ndim, const int64_t* shape, 
                 "use the direct engine for fp64 grids");
   if (engine == SPIDER_ENGINE_DIRECT && low)
     return fail(SPIDER_ERR_UNSUPPORTED, "the direct engine runs fp32/fp64 grids only");
-  if (matrix && (o.split < 1 || o.split > 3 || (o.split == 3 && low)))
-    return fail(SPIDER_ERR_INVALID, "split must be 1 or 2 (16-bit carry) or 1..3 (fp32 carry)");
+  if (matrix && (o.split < 1 || o.split > 3 || (o.split == 3 && low && ndim != 1)))
+    return fail(SPIDER_ERR_INVALID, "split must be 1 or 2 (16-bit carry), 1..3 (fp32 carry, or a 16-bit carry on a "
+                                    "1-D line)");
   if (engine == SPIDER_ENGINE_DIRECT && ndim == 3 && radius > 2)
     return fail(SPIDER_ERR_UNSUPPORTED, "direct engine: 3-D radius up to 2");
   if (matrix && ndim == 3 && radius > 1)
@@ -874,7 +884,8 @@ static uint64_t pair_launch_instructions(const spider_plan_s* p, const BandGrid&
 // fused; each iteration issues T band products per LDS row (hi, and lo with the
 // input split), one smfmac or two dense mfma each.
 static uint64_t line_launch_instructions(const spider_plan_s* p, const BandGrid& g, int T) {
-  const bool f32 = p->carry == SPIDER_F32;
+  // the fp32-level kernels: fp32 carry, or (fused steps) a 16-bit carry with split 3
+  const bool f32 = p->carry == SPIDER_F32 || (line_split_levels(p) && T > 1);
   const int U = (f32 && T > 1) ? 4 : 8;
   const int ns = (f32 && p->split == 3) ? 2 : 1;
   uint64_t iters = 0;

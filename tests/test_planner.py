@@ -365,8 +365,11 @@ def test_invalid_arguments_rejected_without_gpu():
     shp3 = (ctypes.c_int64 * 3)(16, 16, 16)
     o = opts(carry=0, engine=1)  # no matrix engine takes an fp64 carry
     assert L.spider_plan(w3.ctypes.data, 3, shp3, 1, ctypes.byref(o), ctypes.byref(h)) == 2
-    o = opts(carry=2, engine=1, split=3)  # the input split needs an fp32 carry
+    o = opts(carry=2, engine=1, split=3)  # with a 16-bit carry, split 3 exists on 1-D lines only
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
+    assert "1-D" in L.spider_last_error().decode()
+    o = opts(carry=2, engine=1, split=3)
+    assert L.spider_plan(w3.ctypes.data, 3, shp3, 1, ctypes.byref(o), ctypes.byref(h)) == 1
     o = opts(carry=1, engine=1, split=4)
     assert L.spider_plan(w.ctypes.data, 2, shp, 1, ctypes.byref(o), ctypes.byref(h)) == 1
     o = opts(carry=2, engine=1, operand=3)  # operand must be the 16-bit carry type
