@@ -28,6 +28,7 @@ CASES = [
     ("box2d49p_10240", dict(carry="f32", engine="sparse", split=2, time_block=2), 5, True),
     ("star2d13p_8192", dict(carry="f32", engine="dense", split=3, time_block=1), 3, True),
     ("box2d49p_10240", dict(carry="f32", engine="sparse", split=3, time_block=3), 3, False),
+    ("1d3p_10240000", dict(carry="f16", engine="sparse", split=3, time_block=4), 11, False),
 ]
 i = int(sys.argv[1])
 name, kw, steps, small = CASES[i]

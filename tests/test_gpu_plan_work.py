@@ -25,6 +25,7 @@ COUNTED = [
     ("box2d49p_10240", True, dict(carry="f32", engine="sparse", split=2, time_block=2), 5, 3, 27744),
     ("star2d13p_8192", True, dict(carry="f32", engine="dense", split=3, time_block=1), 3, 3, 55296),
     ("box2d49p_10240", False, dict(carry="f32", engine="sparse", split=3, time_block=3), 3, 1, 12415680),
+    ("1d3p_10240000", False, dict(carry="f16", engine="sparse", split=3, time_block=4), 11, 4, 1154648),
 ]
 
 
