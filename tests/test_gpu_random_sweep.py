@@ -49,7 +49,8 @@ def draw_case(rng, scale=1):
             opts["split"] = int(rng.choice([2, 3]))
     else:
         opts["engine"] = str(rng.choice(["sparse", "dense"]))
-        opts["split"] = int(rng.choice([1, 2]))
+        # split 3 with a 16-bit grid: 1-D lines (rounded once per fused launch)
+        opts["split"] = int(rng.choice([1, 2, 3] if ndim == 1 else [1, 2]))
     opts["band_height"] = int(rng.choice([0, 8, 16]))
     opts["time_block"] = int(rng.integers(0, 5))
     opts["tile_h"] = int(rng.choice([0, 0, 1, 2, 7, 16, 33, 100]))
